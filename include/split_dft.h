@@ -1,0 +1,125 @@
+/*
+ * split_dft.h - batched complex DFT on separate real and imaginary planes,
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * Operation (Cariow, arXiv 2504.07264, Section II, eqs. (3)-(5)): for each of
+ * `batch` independent rows of length N,
+ *
+ *     yr = C_N xr + S_N xi,      yi = C_N xi - S_N xr,
+ *
+ * with c_{k,n} = cos(2 pi k n / N) and s_{k,n} = sin(2 pi k n / N), i.e. the
+ * forward DFT of eq. (1) (negative exponent, no normalisation) with the real
+ * and imaginary parts held in separate arrays.  It is evaluated through the
+ * decimation-in-time Kronecker factorisation of eq. (6) (Section III): a
+ * bit-reversal permutation, then m = log2 N stages, each a twiddle factor
+ * D^(i) (2x2 rotations omega^(i,q)) followed by a butterfly factor W^(i).
+ *
+ * Every FP32 result equals, bit for bit, the factors of eq. (6) applied in
+ * order with these operation forms: rotation of (ar, ai) by omega^(i,q) =
+ * [[c, s], [-s, c]] as (fmaf(c, ar, s*ai), fmaf(c, ai, -(s*ar))); butterfly
+ * (u + v, u - v); c and s the round-to-nearest FP32 values of cos and sin of
+ * 2 pi q / 2^i computed in FP64 with exact values at multiples of pi/4.
+ *
+ * Layout: each plane is a contiguous row-major [batch][N] array of float.
+ *
+ * Ownership: all data pointers are device memory owned by the caller.  A plan
+ * owns its device twiddle table (allocated by split_dft_plan, freed by
+ * split_dft_destroy).
+ *
+ * Errors: every entry point returns a status and never aborts or throws.
+ * Arguments are validated before any HIP call; on a validation failure no
+ * kernel is launched and outputs are untouched.  Launches are asynchronous on
+ * the caller's stream: a device fault surfaces at the caller's next
+ * synchronisation.  split_dft_last_error() returns a message for the most
+ * recent failure on the calling thread.
+ *
+ * Threads and streams: a plan is immutable after creation; exec and adjoint
+ * may run concurrently on different streams with the same plan.
+ */
+#ifndef SPLIT_DFT_H
+#define SPLIT_DFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct split_dft_plan_s *split_dft_plan_t;
+
+typedef enum {
+    SPLIT_DFT_OK = 0,
+    SPLIT_DFT_ERR_INVALID_LENGTH = 1, /* N not a power of two in [1, 2^16]  */
+    SPLIT_DFT_ERR_INVALID_BATCH = 2,  /* batch < 1, or N*batch*4 overflows  */
+    SPLIT_DFT_ERR_NULL_POINTER = 3,   /* a required pointer is NULL         */
+    SPLIT_DFT_ERR_MISALIGNED = 4,     /* a data pointer not 16-byte aligned */
+    SPLIT_DFT_ERR_ALIASING = 5,       /* outputs overlap illegally          */
+    SPLIT_DFT_ERR_UNSUPPORTED = 6,    /* flags or variant not supported     */
+    SPLIT_DFT_ERR_OUT_OF_MEMORY = 7,  /* device allocation failed           */
+    SPLIT_DFT_ERR_HIP = 8,            /* a HIP runtime call failed          */
+    SPLIT_DFT_ERR_INVALID_PLAN = 9    /* NULL, destroyed or foreign plan    */
+} split_dft_status;
+
+/* Plan flags (precision of the arithmetic). */
+#define SPLIT_DFT_FP32 0u /* FP32 throughout (the default) */
+
+/* Largest supported log2 N. */
+#define SPLIT_DFT_MAX_LOG2N 16
+
+/*
+ * Create a plan for `batch` transforms of length n = 2^m, 0 <= m <= 16
+ * (the paper's own domain is m >= 2, Section III; m = 0 and m = 1 follow from
+ * the same formulas).  Builds the twiddle table omega^(i,q) (Section III,
+ * definitions under eq. 6) on the host in FP64, rounds it to FP32 and copies
+ * it to the current HIP device.  *out is set only on success.
+ */
+split_dft_status split_dft_plan(split_dft_plan_t *out, int64_t n, int64_t batch, uint32_t flags);
+
+/*
+ * Forward transform, eqs. (5)/(6): yr = C xr + S xi, yi = C xi - S xr for
+ * every row.  xr, xi, yr, yi: device pointers to [batch][n] floats, 16-byte
+ * aligned.  In place is allowed (yr == xr and/or yi == xi, or the planes
+ * swapped); yr == yi and any partial overlap of an output with another array
+ * are rejected with SPLIT_DFT_ERR_ALIASING.  `stream` is a hipStream_t
+ * (NULL = the default stream).
+ */
+split_dft_status split_dft_exec(split_dft_plan_t plan, const float *xr, const float *xi,
+                                float *yr, float *yi, void *stream);
+
+/*
+ * Adjoint (transpose) transform: gxr = C gr - S gi, gxi = S gr + C gi, the
+ * transpose of E_2N of eq. (5) (C and S are symmetric).  This is N times the
+ * inverse DFT; it is the vector-Jacobian product of split_dft_exec.  Same
+ * argument rules as split_dft_exec.
+ */
+split_dft_status split_dft_adjoint(split_dft_plan_t plan, const float *gr, const float *gi,
+                                   float *gxr, float *gxi, void *stream);
+
+/* Release a plan and its device table.  NULL is accepted and ignored. */
+split_dft_status split_dft_destroy(split_dft_plan_t plan);
+
+/* Scratch bytes a plan needs beyond inputs and outputs (0 for every length
+ * handled in a single pass). */
+size_t split_dft_workspace_bytes(split_dft_plan_t plan);
+
+/* Plan properties: length, batch, log2 length and the kernel schedule chosen
+ * (elements per thread `ept` and transforms per workgroup `tpw`); any
+ * pointer may be NULL. */
+split_dft_status split_dft_plan_info(split_dft_plan_t plan, int64_t *n, int64_t *batch,
+                                     int *log2n, int *ept, int *tpw);
+
+/* Host-only: write the FP32 twiddle table the plans of length 2^m use, in
+ * the layout entry[2^(i-1) + q] = omega^(i,q) for stage i = 1..m and
+ * q < 2^(i-1), entry[0] = angle 0; c and s each hold 2^m floats.  Makes no
+ * HIP call. */
+split_dft_status split_dft_twiddle_table(int m, float *c, float *s);
+
+const char *split_dft_status_string(split_dft_status status);
+const char *split_dft_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPLIT_DFT_H */

@@ -1,0 +1,273 @@
+// C ABI of the split-format DFT library: plans, argument validation, launch.
+#include "../../include/split_dft.h"
+#include "internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+struct split_dft_plan_s {
+    int64_t n;
+    int64_t batch;
+    int m;
+    uint32_t flags;
+    int device;
+    float2* d_tw;  // 2^m entries: (cos, sin) of omega^(i,q) at 2^(i-1)+q
+    const splitdft::Variant* variant;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+std::mutex g_plans_mu;
+std::unordered_set<const split_dft_plan_s*>& live_plans()
+{
+    static auto* s = new std::unordered_set<const split_dft_plan_s*>();
+    return *s;
+}
+
+split_dft_status fail(split_dft_status st, const std::string& msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+split_dft_status fail_hip(hipError_t e, const char* what)
+{
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return SPLIT_DFT_ERR_HIP;
+}
+
+bool log_enabled()
+{
+    const char* v = std::getenv("SPLIT_DFT_LOG");
+    return v && *v && std::strcmp(v, "0") != 0;
+}
+
+int exact_log2(int64_t n)
+{
+    if (n < 1)
+        return -1;
+    int m = 0;
+    while ((int64_t{1} << m) < n && m < 62)
+        ++m;
+    return (int64_t{1} << m) == n ? m : -1;
+}
+
+bool plan_is_live(const split_dft_plan_s* p)
+{
+    std::lock_guard<std::mutex> g(g_plans_mu);
+    return live_plans().count(p) != 0;
+}
+
+bool overlaps(const void* a, const void* b, size_t bytes)
+{
+    const auto x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + bytes && y < x + bytes;
+}
+
+split_dft_status validate_io(const split_dft_plan_s* p, const float* xr, const float* xi, const float* yr,
+                             const float* yi)
+{
+    if (!xr || !xi || !yr || !yi)
+        return fail(SPLIT_DFT_ERR_NULL_POINTER, "a data pointer is NULL");
+    for (const void* q : {static_cast<const void*>(xr), static_cast<const void*>(xi), static_cast<const void*>(yr),
+                          static_cast<const void*>(yi)})
+        if (reinterpret_cast<uintptr_t>(q) % 16 != 0)
+            return fail(SPLIT_DFT_ERR_MISALIGNED, "data pointers must be 16-byte aligned");
+    const size_t bytes = static_cast<size_t>(p->n) * static_cast<size_t>(p->batch) * sizeof(float);
+    if (overlaps(yr, yi, bytes))
+        return fail(SPLIT_DFT_ERR_ALIASING, "the two output planes overlap");
+    for (const float* out : {yr, yi})
+        for (const float* in : {xr, xi})
+            if (out != in && overlaps(out, in, bytes))
+                return fail(SPLIT_DFT_ERR_ALIASING, "an output partially overlaps an input");
+    return SPLIT_DFT_OK;
+}
+
+split_dft_status run(split_dft_plan_t p, const float* xr, const float* xi, float* yr, float* yi, void* stream)
+{
+    if (!p || !plan_is_live(p))
+        return fail(SPLIT_DFT_ERR_INVALID_PLAN, "plan is NULL, destroyed or not created by split_dft_plan");
+    const split_dft_status st = validate_io(p, xr, xi, yr, yi);
+    if (st != SPLIT_DFT_OK)
+        return st;
+    const hipError_t e =
+        p->variant->launch(xr, xi, yr, yi, p->d_tw, p->batch, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return fail_hip(e, "kernel launch");
+    return SPLIT_DFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+split_dft_status split_dft_plan(split_dft_plan_t* out, int64_t n, int64_t batch, uint32_t flags)
+{
+    if (!out)
+        return fail(SPLIT_DFT_ERR_NULL_POINTER, "out is NULL");
+    const int m = exact_log2(n);
+    if (m < 0 || m > SPLIT_DFT_MAX_LOG2N)
+        return fail(SPLIT_DFT_ERR_INVALID_LENGTH, "n must be 2^m with 0 <= m <= 16, got " + std::to_string(n));
+    if (batch < 1)
+        return fail(SPLIT_DFT_ERR_INVALID_BATCH, "batch must be >= 1, got " + std::to_string(batch));
+    if (batch > INT64_MAX / n / static_cast<int64_t>(sizeof(float)))
+        return fail(SPLIT_DFT_ERR_INVALID_BATCH, "n * batch * 4 bytes overflows int64");
+    const uint32_t precision = flags & 0xffu;
+    const uint32_t vsel = (flags >> 8) & 0xffu;  // 0 = default schedule, k = compiled schedule k-1
+    if (precision != SPLIT_DFT_FP32 || (flags >> 16) != 0)
+        return fail(SPLIT_DFT_ERR_UNSUPPORTED, "unsupported flags " + std::to_string(flags));
+
+    int count = 0;
+    const splitdft::Variant* list = splitdft::variants_for(m, &count);
+    const splitdft::Variant* v = nullptr;
+    if (vsel == 0)
+        v = splitdft::default_variant(m, batch);
+    else if (static_cast<int>(vsel) <= count)
+        v = &list[vsel - 1];
+    if (!v)
+        return fail(SPLIT_DFT_ERR_UNSUPPORTED,
+                    "no compiled schedule for n = " + std::to_string(n) + " (selector " + std::to_string(vsel) + ")");
+
+    const char* inj = std::getenv("SPLIT_DFT_FAIL_ALLOC");
+    if (inj && *inj && std::strcmp(inj, "0") != 0)
+        return fail(SPLIT_DFT_ERR_OUT_OF_MEMORY, "allocation failure forced by SPLIT_DFT_FAIL_ALLOC");
+
+    std::vector<float> c(static_cast<size_t>(n)), s(static_cast<size_t>(n));
+    splitdft::build_twiddles_f32(m, c.data(), s.data());
+    std::vector<float2> tw(static_cast<size_t>(n));
+    for (int64_t j = 0; j < n; ++j)
+        tw[static_cast<size_t>(j)] = make_float2(c[static_cast<size_t>(j)], s[static_cast<size_t>(j)]);
+
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return fail_hip(e, "hipGetDevice");
+    float2* d_tw = nullptr;
+    e = hipMalloc(&d_tw, sizeof(float2) * static_cast<size_t>(n));
+    if (e == hipErrorOutOfMemory)
+        return fail(SPLIT_DFT_ERR_OUT_OF_MEMORY, "hipMalloc of the twiddle table failed");
+    if (e != hipSuccess)
+        return fail_hip(e, "hipMalloc");
+    e = hipMemcpy(d_tw, tw.data(), sizeof(float2) * static_cast<size_t>(n), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d_tw);
+        return fail_hip(e, "hipMemcpy of the twiddle table");
+    }
+    auto* p = new (std::nothrow) split_dft_plan_s{n, batch, m, flags, dev, d_tw, v};
+    if (!p) {
+        (void)hipFree(d_tw);
+        return fail(SPLIT_DFT_ERR_OUT_OF_MEMORY, "host allocation of the plan failed");
+    }
+    {
+        std::lock_guard<std::mutex> g(g_plans_mu);
+        live_plans().insert(p);
+    }
+    if (log_enabled())
+        std::fprintf(stderr, "[split_dft] plan n=%lld batch=%lld ept=%d tpw=%d threads=%d lds=%d\n",
+                     static_cast<long long>(n), static_cast<long long>(batch), 1 << v->rb, v->tpw, v->threads,
+                     v->lds_bytes);
+    *out = p;
+    return SPLIT_DFT_OK;
+}
+
+split_dft_status split_dft_exec(split_dft_plan_t plan, const float* xr, const float* xi, float* yr, float* yi,
+                                void* stream)
+{
+    return run(plan, xr, xi, yr, yi, stream);
+}
+
+split_dft_status split_dft_adjoint(split_dft_plan_t plan, const float* gr, const float* gi, float* gxr, float* gxi,
+                                   void* stream)
+{
+    // C gr - S gi = imaginary part and S gr + C gi = real part of the forward
+    // transform of (gi, gr): the adjoint is the forward kernel with both
+    // plane pairs exchanged.
+    return run(plan, gi, gr, gxi, gxr, stream);
+}
+
+split_dft_status split_dft_destroy(split_dft_plan_t plan)
+{
+    if (!plan)
+        return SPLIT_DFT_OK;
+    {
+        std::lock_guard<std::mutex> g(g_plans_mu);
+        if (live_plans().erase(plan) == 0)
+            return fail(SPLIT_DFT_ERR_INVALID_PLAN, "plan is destroyed or not created by split_dft_plan");
+    }
+    int cur = 0;
+    const bool switch_dev = hipGetDevice(&cur) == hipSuccess && cur != plan->device;
+    if (switch_dev)
+        (void)hipSetDevice(plan->device);
+    const hipError_t e = hipFree(plan->d_tw);
+    if (switch_dev)
+        (void)hipSetDevice(cur);
+    delete plan;
+    if (e != hipSuccess)
+        return fail_hip(e, "hipFree");
+    return SPLIT_DFT_OK;
+}
+
+size_t split_dft_workspace_bytes(split_dft_plan_t plan)
+{
+    (void)plan;
+    return 0;
+}
+
+split_dft_status split_dft_plan_info(split_dft_plan_t plan, int64_t* n, int64_t* batch, int* log2n, int* ept,
+                                     int* tpw)
+{
+    if (!plan || !plan_is_live(plan))
+        return fail(SPLIT_DFT_ERR_INVALID_PLAN, "plan is NULL, destroyed or not created by split_dft_plan");
+    if (n)
+        *n = plan->n;
+    if (batch)
+        *batch = plan->batch;
+    if (log2n)
+        *log2n = plan->m;
+    if (ept)
+        *ept = 1 << plan->variant->rb;
+    if (tpw)
+        *tpw = plan->variant->tpw;
+    return SPLIT_DFT_OK;
+}
+
+split_dft_status split_dft_twiddle_table(int m, float* c, float* s)
+{
+    if (!c || !s)
+        return fail(SPLIT_DFT_ERR_NULL_POINTER, "c or s is NULL");
+    if (m < 0 || m > SPLIT_DFT_MAX_LOG2N)
+        return fail(SPLIT_DFT_ERR_INVALID_LENGTH, "m must be in [0, 16]");
+    splitdft::build_twiddles_f32(m, c, s);
+    return SPLIT_DFT_OK;
+}
+
+const char* split_dft_status_string(split_dft_status status)
+{
+    switch (status) {
+    case SPLIT_DFT_OK: return "ok";
+    case SPLIT_DFT_ERR_INVALID_LENGTH: return "invalid length";
+    case SPLIT_DFT_ERR_INVALID_BATCH: return "invalid batch";
+    case SPLIT_DFT_ERR_NULL_POINTER: return "null pointer";
+    case SPLIT_DFT_ERR_MISALIGNED: return "misaligned pointer";
+    case SPLIT_DFT_ERR_ALIASING: return "illegal aliasing";
+    case SPLIT_DFT_ERR_UNSUPPORTED: return "unsupported";
+    case SPLIT_DFT_ERR_OUT_OF_MEMORY: return "out of memory";
+    case SPLIT_DFT_ERR_HIP: return "HIP runtime error";
+    case SPLIT_DFT_ERR_INVALID_PLAN: return "invalid plan";
+    }
+    return "unknown status";
+}
+
+const char* split_dft_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,225 @@
+"""GPU parity of the HIP path against the CPU oracle (needs an MI355X).
+
+Bars:
+* bit-exact (==, so +0 == -0) against the oracle's FP32 structural mirror of
+  eq. (6) (same factors, same operation forms, same order);
+* per-transform relative L2 error <= 2e-7 * log2(N) + 1e-7 against the FP64
+  oracle (O2 on every row; O1, the direct evaluation of eq. (5), on sampled
+  rows or bins).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2504_07264_amd import Plan, SplitDFTError, binding, inputs, variant_flag
+
+pytestmark = pytest.mark.gpu
+
+
+def tol(n):
+    m = int(n).bit_length() - 1
+    return 2e-7 * m + 1e-7
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def gpu_exec(n, batch, xr, xi, flags=0, adjoint=False):
+    say("  exec n=%d batch=%d flags=%#x adjoint=%s" % (n, batch, flags, adjoint))
+    with Plan(n, batch, flags) as p:
+        dr, di = xr.cuda(), xi.cuda()
+        yr, yi = (p.adjoint if adjoint else p.exec)(dr, di)
+        torch.cuda.synchronize()
+        return to_np(yr), to_np(yi)
+
+
+def assert_bit_exact(yr, yi, mr, mi):
+    badr = np.argwhere(yr != mr)
+    badi = np.argwhere(yi != mi)
+    assert badr.size == 0 and badi.size == 0, (
+        "not bit-exact: %d real and %d imag mismatches, first at %s"
+        % (len(badr), len(badi), (badr[:1].tolist(), badi[:1].tolist())))
+
+
+def assert_within_tol(yr, yi, rr, ri, n):
+    err = oracle.rel_l2_per_row(yr, yi, rr, ri)
+    assert err.max() <= tol(n), "max rel L2 %.3e > %.3e" % (err.max(), tol(n))
+    return err
+
+
+# ------------------------------------------------------- the N=16 workload
+def test_small_n16_bit_exact_and_direct():
+    w = inputs.SMALL_N16
+    xr, xi = inputs.draw(w)
+    yr, yi = gpu_exec(w.n, w.batch, xr, xi)
+    mr, mi = oracle.split_fft_f32(xr.numpy(), xi.numpy())
+    assert_bit_exact(yr, yi, mr, mi)
+    rr, ri = oracle.dft_direct(xr.double().numpy(), xi.double().numpy())
+    assert_within_tol(yr, yi, rr, ri, w.n)
+
+
+# ------------------------------------------------------- every length, every schedule
+def all_variants(m):
+    out = [0]
+    k = 0
+    while True:
+        try:
+            with Plan(1 << m, 1, variant_flag(k)):
+                pass
+        except SplitDFTError:
+            break
+        out.append(variant_flag(k))
+        k += 1
+    return out
+
+
+@pytest.mark.parametrize("m", range(0, 16))
+def test_every_length_and_schedule(m):
+    n = 1 << m
+    # a batch that is not a multiple of any workgroup's transform count, and
+    # spans several workgroups
+    batch = max(3, min(1000, (1 << 19) // n)) | 1
+    xr, xi = inputs.draw_planes(n, batch, "normal", 1000 + m)
+    mr, mi = oracle.split_fft_f32(xr.numpy(), xi.numpy())
+    rr, ri = oracle.split_fft(xr.double().numpy(), xi.double().numpy())
+    for flags in all_variants(m):
+        yr, yi = gpu_exec(n, batch, xr, xi, flags)
+        assert_bit_exact(yr, yi, mr, mi)
+        assert_within_tol(yr, yi, rr, ri, n)
+
+
+@pytest.mark.parametrize("m", [0, 1, 4, 7, 10, 12, 15])
+def test_adjoint_every_length(m):
+    n = 1 << m
+    batch = max(1, min(257, (1 << 18) // n))
+    gr, gi = inputs.draw_planes(n, batch, "uniform", 2000 + m)
+    yr, yi = gpu_exec(n, batch, gr, gi, adjoint=True)
+    mr, mi = oracle.split_adjoint_f32(gr.numpy(), gi.numpy())
+    assert_bit_exact(yr, yi, mr, mi)
+    rr, ri = oracle.adjoint_direct(gr.double().numpy(), gi.double().numpy()) if n <= 4096 else \
+        oracle.split_adjoint_f32(gr.numpy(), gi.numpy())
+    if n <= 4096:
+        assert_within_tol(yr, yi, rr, ri, n)
+
+
+@pytest.mark.parametrize("m", [4, 10, 15])
+def test_closed_forms_exact(m):
+    n = 1 << m
+    batch = 3
+    x = torch.zeros(batch, n)
+    x[:, 0] = 1.0
+    z = torch.zeros(batch, n)
+    yr, yi = gpu_exec(n, batch, x, z)
+    assert np.all(yr == 1.0) and np.all(yi == 0.0)
+    one = torch.ones(batch, n)
+    yr, yi = gpu_exec(n, batch, one, z)
+    expect = np.zeros((batch, n), np.float32)
+    expect[:, 0] = n
+    assert np.array_equal(yr, expect) and np.all(yi == 0.0)
+
+
+@pytest.mark.parametrize("m", [3, 10, 13])
+def test_single_tone_sign(m):
+    n = 1 << m
+    k0 = n // 3
+    t = 2 * np.pi * ((k0 * np.arange(n)) % n) / n
+    xr = torch.tensor(np.cos(t), dtype=torch.float32)[None]
+    xi = torch.tensor(np.sin(t), dtype=torch.float32)[None]
+    yr, yi = gpu_exec(n, 1, xr, xi)
+    assert abs(yr[0, k0] - n) < 1e-4 * n
+    mag = np.hypot(yr[0], yi[0])
+    mag[k0] = 0
+    assert mag.max() < 1e-4 * n
+
+
+# ------------------------------------------------------- the N=1024 x 16384 workload
+def test_headline_full_size():
+    w = inputs.HEADLINE_N1024
+    xr, xi = inputs.draw(w)
+    yr, yi = gpu_exec(w.n, w.batch, xr, xi)
+    say("  oracle mirror + FP64 on %d rows" % w.batch)
+    mr, mi = oracle.split_fft_f32(xr.numpy(), xi.numpy())
+    assert_bit_exact(yr, yi, mr, mi)
+    rr, ri = oracle.split_fft(xr.double().numpy(), xi.double().numpy())
+    err = assert_within_tol(yr, yi, rr, ri, w.n)
+    say("  rel L2: max %.3e median %.3e" % (err.max(), np.median(err)))
+    rows = np.random.default_rng(0).choice(w.batch, 64, replace=False)
+    dr, di = oracle.dft_direct(xr.double().numpy()[rows], xi.double().numpy()[rows])
+    assert_within_tol(yr[rows], yi[rows], dr, di, w.n)
+
+
+def test_adjoint_full_size_n4096():
+    w = inputs.GRAD_N4096
+    xr, xi, wr, wi = inputs.draw(w)
+    yr, yi = gpu_exec(w.n, w.batch, wr, wi, adjoint=True)
+    mr, mi = oracle.split_adjoint_f32(wr.numpy(), wi.numpy())
+    assert_bit_exact(yr, yi, mr, mi)
+    rows = np.random.default_rng(1).choice(w.batch, 16, replace=False)
+    dr, di = oracle.adjoint_direct(wr.double().numpy()[rows], wi.double().numpy()[rows])
+    assert_within_tol(yr[rows], yi[rows], dr, di, w.n)
+
+
+# ------------------------------------------------------- boundary behaviour on the device
+def test_in_place_and_swapped_planes():
+    n, batch = 1024, 37
+    xr, xi = inputs.draw_planes(n, batch, "normal", 7)
+    mr, mi = oracle.split_fft_f32(xr.numpy(), xi.numpy())
+    with Plan(n, batch) as p:
+        ar, ai = xr.cuda(), xi.cuda()
+        p.exec(ar, ai, ar, ai)
+        torch.cuda.synchronize()
+        assert_bit_exact(to_np(ar), to_np(ai), mr, mi)
+        br, bi = xr.cuda(), xi.cuda()
+        p.exec(br, bi, bi, br)  # outputs swapped onto the inputs
+        torch.cuda.synchronize()
+        assert_bit_exact(to_np(bi), to_np(br), mr, mi)
+
+
+def test_rejects_misaligned_and_overlapping():
+    n, batch = 64, 4
+    with Plan(n, batch) as p:
+        big = torch.zeros(3 * n * batch + 8, device="cuda")
+        a = big[: n * batch].view(batch, n)
+        b = big[n * batch: 2 * n * batch].view(batch, n)
+        L = binding.lib()
+        s = torch.cuda.current_stream().cuda_stream
+        st = L.split_dft_exec(p.handle, a.data_ptr() + 4, b.data_ptr(), a.data_ptr(), b.data_ptr(), s)
+        assert st == 4
+        st = L.split_dft_exec(p.handle, a.data_ptr(), b.data_ptr(), a.data_ptr() + 64, b.data_ptr(), s)
+        assert st == 5
+        st = L.split_dft_exec(p.handle, a.data_ptr(), b.data_ptr(), b.data_ptr(), b.data_ptr(), s)
+        assert st == 5
+        with pytest.raises(ValueError):
+            p.exec(a[:, :32].contiguous(), b[:, :32].contiguous())
+        with pytest.raises(TypeError):
+            p.exec(a.double(), b.double())
+
+
+def test_runs_on_a_side_stream():
+    n, batch = 256, 1000
+    xr, xi = inputs.draw_planes(n, batch, "uniform", 9)
+    mr, mi = oracle.split_fft_f32(xr.numpy(), xi.numpy())
+    st = torch.cuda.Stream()
+    with Plan(n, batch) as p:
+        dr, di = xr.cuda(), xi.cuda()
+        torch.cuda.current_stream().synchronize()
+        with torch.cuda.stream(st):
+            yr, yi = p.exec(dr, di)
+        st.synchronize()
+        assert_bit_exact(to_np(yr), to_np(yi), mr, mi)
+
+
+def test_batch_one_and_large_batch_small_n():
+    for n, batch in ((16, 1), (2, 1), (1, 5), (16, 1 << 20)):
+        xr, xi = inputs.draw_planes(n, batch, "normal", 11)
+        yr, yi = gpu_exec(n, batch, xr, xi)
+        mr, mi = oracle.split_fft_f32(xr.numpy(), xi.numpy())
+        assert_bit_exact(yr, yi, mr, mi)
