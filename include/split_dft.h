@@ -109,6 +109,11 @@ size_t split_dft_workspace_bytes(split_dft_plan_t plan);
 split_dft_status split_dft_plan_info(split_dft_plan_t plan, int64_t *n, int64_t *batch,
                                      int *log2n, int *ept, int *tpw);
 
+/* Write a NUL-terminated description of the plan's kernel schedule (elements
+ * per thread, transforms per workgroup, LDS bytes and data-movement options)
+ * into buf, truncated to len bytes.  Makes no HIP call. */
+split_dft_status split_dft_plan_describe(split_dft_plan_t plan, char *buf, size_t len);
+
 /* Host-only: write the FP32 twiddle table the plans of length 2^m use, in
  * the layout entry[2^(i-1) + q] = omega^(i,q) for stage i = 1..m and
  * q < 2^(i-1), entry[0] = angle 0; c and s each hold 2^m floats.  Makes no

@@ -31,7 +31,7 @@ MAX_LOG2N = 16
 
 EXPORTED = (
     "split_dft_plan", "split_dft_exec", "split_dft_adjoint", "split_dft_destroy",
-    "split_dft_workspace_bytes", "split_dft_plan_info", "split_dft_twiddle_table",
+    "split_dft_workspace_bytes", "split_dft_plan_info", "split_dft_plan_describe", "split_dft_twiddle_table",
     "split_dft_status_string", "split_dft_last_error",
 )
 
@@ -71,6 +71,8 @@ def lib() -> ctypes.CDLL:
         pi64 = ctypes.POINTER(i64)
         L.split_dft_plan_info.argtypes = [vp, pi64, pi64, pi, pi, pi]
         L.split_dft_plan_info.restype = ci
+        L.split_dft_plan_describe.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
+        L.split_dft_plan_describe.restype = ci
         L.split_dft_twiddle_table.argtypes = [ci, vp, vp]
         L.split_dft_twiddle_table.restype = ci
         L.split_dft_status_string.argtypes = [ci]
@@ -132,6 +134,11 @@ class Plan:
         check(lib().split_dft_plan_info(self._h, ctypes.byref(n), ctypes.byref(b), ctypes.byref(m),
                                         ctypes.byref(ept), ctypes.byref(tpw)))
         return {"n": n.value, "batch": b.value, "log2n": m.value, "ept": ept.value, "tpw": tpw.value}
+
+    def describe(self) -> str:
+        buf = ctypes.create_string_buffer(256)
+        check(lib().split_dft_plan_describe(self._h, buf, len(buf)))
+        return buf.value.decode()
 
     def workspace_bytes(self) -> int:
         return int(lib().split_dft_workspace_bytes(self._h))

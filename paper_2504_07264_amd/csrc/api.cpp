@@ -173,9 +173,11 @@ split_dft_status split_dft_plan(split_dft_plan_t* out, int64_t n, int64_t batch,
         live_plans().insert(p);
     }
     if (log_enabled())
-        std::fprintf(stderr, "[split_dft] plan n=%lld batch=%lld ept=%d tpw=%d threads=%d lds=%d\n",
+        std::fprintf(stderr,
+                     "[split_dft] plan n=%lld batch=%lld ept=%d tpw=%d threads=%d lds=%d split=%d nt=%d twl=%d "
+                     "wpe=%d\n",
                      static_cast<long long>(n), static_cast<long long>(batch), 1 << v->rb, v->tpw, v->threads,
-                     v->lds_bytes);
+                     v->lds_bytes, v->split, v->nt, v->twl, v->wpe);
     *out = p;
     return SPLIT_DFT_OK;
 }
@@ -238,6 +240,19 @@ split_dft_status split_dft_plan_info(split_dft_plan_t plan, int64_t* n, int64_t*
         *ept = 1 << plan->variant->rb;
     if (tpw)
         *tpw = plan->variant->tpw;
+    return SPLIT_DFT_OK;
+}
+
+split_dft_status split_dft_plan_describe(split_dft_plan_t plan, char* buf, size_t len)
+{
+    if (!plan || !plan_is_live(plan))
+        return fail(SPLIT_DFT_ERR_INVALID_PLAN, "plan is NULL, destroyed or not created by split_dft_plan");
+    if (!buf || len == 0)
+        return fail(SPLIT_DFT_ERR_NULL_POINTER, "buf is NULL or len is 0");
+    const splitdft::Variant* v = plan->variant;
+    std::snprintf(buf, len, "ept=%d tpw=%d threads=%d lds=%d split=%d nt=%d twl=%d wpe=%d f4io=%d", 1 << v->rb,
+                  v->tpw, v->threads, v->lds_bytes, v->split ? 1 : 0, v->nt ? 1 : 0, v->twl ? 1 : 0, v->wpe,
+                  v->f4io ? 1 : 0);
     return SPLIT_DFT_OK;
 }
 

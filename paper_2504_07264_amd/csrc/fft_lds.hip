@@ -68,8 +68,10 @@ __device__ __forceinline__ void rotate(float& ar, float& ai, float c, float s)
     ai = ti;
 }
 
-// Stages S+1 .. S+RP of eq. (6) on the E registers of one thread.
-template <int E, int LT, int S, int RP>
+// Stages S+1 .. S+RP of eq. (6) on the E registers of one thread.  For S > 0
+// the twiddle of table entry idx is read at tw[idx - TWOFF] (TWOFF > 0 when
+// only the upper part of the table is staged).
+template <int E, int LT, int S, int RP, int TWOFF = 0>
 __device__ __forceinline__ void stages(float (&vr)[E], float (&vi)[E], int t, const float2* __restrict__ tw)
 {
 #pragma unroll
@@ -97,7 +99,7 @@ __device__ __forceinline__ void stages(float (&vr)[E], float (&vi)[E], int t, co
             } else {
                 const int o = t + ((u >> RP) << LT);
                 const int q = (o & ((1 << S) - 1)) + ((u & (half - 1)) << S);
-                const float2 w = tw[(1 << (S + k - 1)) + q];
+                const float2 w = tw[(1 << (S + k - 1)) - TWOFF + q];
                 rotate(ar, ai, w.x, w.y);
             }
             const float ur = vr[u], ui = vi[u];
@@ -132,7 +134,7 @@ __device__ __forceinline__ void lds_get(float (&v)[E], const float* lds, int t)
 }
 
 // Passes P, P+1, ... : exchange through LDS, then the pass's stages.
-template <int M, int RB, int P, bool SPLIT, int E>
+template <int M, int RB, int P, bool SPLIT, int E, int TWOFF>
 __device__ __forceinline__ void later_passes(float (&vr)[E], float (&vi)[E], float* lr, float* li, int t,
                                              const float2* __restrict__ tw)
 {
@@ -157,64 +159,195 @@ __device__ __forceinline__ void later_passes(float (&vr)[E], float (&vi)[E], flo
             lds_get<E, LT, Cur::S, Cur::RP>(vi, li, t);
             __syncthreads();
         }
-        stages<E, LT, Cur::S, Cur::RP>(vr, vi, t, tw);
-        later_passes<M, RB, P + 1, SPLIT, E>(vr, vi, lr, li, t, tw);
+        stages<E, LT, Cur::S, Cur::RP, TWOFF>(vr, vi, t, tw);
+        later_passes<M, RB, P + 1, SPLIT, E, TWOFF>(vr, vi, lr, li, t, tw);
     }
 }
 
-template <int M, int RB, int TPW, bool SPLIT>
-struct Shape {
+// Compile-time schedule of one kernel instance.
+//   M      log2 of the transform length
+//   RB     log2 of the elements each thread holds (stages per full pass)
+//   TPW    transforms per workgroup
+//   SPLIT  exchange one plane at a time through LDS (half the LDS)
+//   NT     nontemporal hints on the streaming global loads and stores
+//   TWL    twiddles of passes >= 1 staged once per workgroup in LDS
+//   WPE    minimum waves per SIMD the register allocation must allow (1 = any)
+//   F4IO   global loads and stores as 16-byte vectors over the workgroup's
+//          contiguous rows, staged through LDS in both directions
+template <int M_, int RB_, int TPW_, bool SPLIT_, bool NT_, bool TWL_, int WPE_, bool F4IO_ = false>
+struct Cfg {
+    static constexpr int M = M_, RB = RB_, TPW = TPW_, WPE = WPE_;
+    static constexpr bool SPLIT = SPLIT_, NT = NT_, TWL = TWL_, F4IO = F4IO_;
     static constexpr int N = 1 << M;
     static constexpr int E = 1 << RB;
     static constexpr int LT = M - RB;
     static constexpr int T = 1 << LT;
     static constexpr int NP = (M + RB - 1) / RB;
     static constexpr int THREADS = TPW * T;
-    static constexpr int PADN = lds_index(N);
-    static constexpr int LDS_WORDS = (NP > 1) ? TPW * PADN * (SPLIT ? 1 : 2) : 1;
+    // LDS words per transform: the padded length, made odd when one wave
+    // spans many transforms so that their slots start on different banks
+    static constexpr int SLOT = T >= 32 ? lds_index(N) : (lds_index(N) | 1);
+    static constexpr bool USES_XCH = NP > 1 || F4IO;
+    static constexpr int XCH_WORDS = USES_XCH ? TPW * SLOT * (SPLIT ? 1 : 2) : 1;
+    // twiddle entries [2^RB, N) are the ones passes >= 1 read
+    static constexpr int TW_LDS = (TWL && NP > 1) ? (N - E) : 0;
+    static constexpr int LDS_BYTES = 4 * XCH_WORDS + 8 * TW_LDS;
+    static_assert(!F4IO || E >= 4, "16-byte I/O needs at least 4 elements per thread");
 };
 
-template <int M, int RB, int TPW, bool SPLIT>
-__global__ void __launch_bounds__(TPW << (M - RB))
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <bool NT>
+__device__ __forceinline__ float load1(const float* p)
+{
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
+template <bool NT>
+__device__ __forceinline__ void store1(float* p, float v)
+{
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
+template <bool NT>
+__device__ __forceinline__ v4f load4(const float* p)
+{
+    if constexpr (NT)
+        return __builtin_nontemporal_load(reinterpret_cast<const v4f*>(p));
+    else
+        return *reinterpret_cast<const v4f*>(p);
+}
+
+template <bool NT>
+__device__ __forceinline__ void store4(float* p, v4f v)
+{
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, reinterpret_cast<v4f*>(p));
+    else
+        *reinterpret_cast<v4f*>(p) = v;
+}
+
+// 16-byte loads of one plane of the workgroup's rows (valid floats only)
+// into LDS; float f of the block lands in slot f / N at lds_index(f mod N).
+template <class C>
+__device__ __forceinline__ void stage_in(const float* x, float* area, int64_t base, int valid, int tid)
+{
+#pragma unroll
+    for (int c = 0; c < C::E / 4; ++c) {
+        const int f = 4 * (tid + c * C::THREADS);
+        if (f < valid) {
+            const v4f v = load4<C::NT>(x + base + f);
+            float* d = area + (f >> C::M) * C::SLOT + lds_index(f & (C::N - 1));
+            d[0] = v[0];
+            d[1] = v[1];
+            d[2] = v[2];
+            d[3] = v[3];
+        }
+    }
+}
+
+// The reverse of stage_in: LDS slots to 16-byte global stores.
+template <class C>
+__device__ __forceinline__ void stage_out(float* y, const float* area, int64_t base, int valid, int tid)
+{
+#pragma unroll
+    for (int c = 0; c < C::E / 4; ++c) {
+        const int f = 4 * (tid + c * C::THREADS);
+        if (f < valid) {
+            const float* s = area + (f >> C::M) * C::SLOT + lds_index(f & (C::N - 1));
+            store4<C::NT>(y + base + f, v4f{s[0], s[1], s[2], s[3]});
+        }
+    }
+}
+
+// Registers of the first pass from an LDS slot holding a transform in
+// natural order: position u + (t << RB) holds x[rev_LT(t) + (rev_RB(u) << LT)].
+template <class C>
+__device__ __forceinline__ void regs_from_natural(float (&v)[C::E], const float* slot_area, int t)
+{
+    const int tb = rev_bits(t, C::LT);
+#pragma unroll
+    for (int u = 0; u < C::E; ++u)
+        v[u] = slot_area[lds_index(tb + (rev_bits(u, C::RB) << C::LT))];
+}
+
+template <class C>
+__device__ __forceinline__ void regs_to_natural(const float (&v)[C::E], float* slot_area, int t)
+{
+    using Last = Pass<C::M, C::RB, C::NP - 1>;
+#pragma unroll
+    for (int u = 0; u < C::E; ++u)
+        slot_area[lds_index(position<C::LT, Last::S, Last::RP>(t, u))] = v[u];
+}
+
+template <class C>
+__global__ void __launch_bounds__(C::THREADS) __attribute__((amdgpu_waves_per_eu(C::WPE)))
 split_fft_lds_kernel(const float* xr, const float* xi, float* yr, float* yi, const float2* __restrict__ tw,
                      int64_t batch)
 {
-    using Sh = Shape<M, RB, TPW, SPLIT>;
-    constexpr int N = Sh::N, E = Sh::E, LT = Sh::LT, T = Sh::T, NP = Sh::NP;
-    __shared__ float lds[Sh::LDS_WORDS];
+    constexpr int M = C::M, RB = C::RB, TPW = C::TPW;
+    constexpr int N = C::N, E = C::E, LT = C::LT, T = C::T, NP = C::NP;
+    constexpr bool NT = C::NT;
+    __shared__ float lds[C::XCH_WORDS];
+    __shared__ v4f lds_tw4[C::TW_LDS > 0 ? C::TW_LDS / 2 : 1];
 
     const int tid = threadIdx.x;
     const int slot = tid >> LT;
     const int t = tid & (T - 1);
-    const int64_t b = static_cast<int64_t>(blockIdx.x) * TPW + slot;
+    const int64_t b0 = static_cast<int64_t>(blockIdx.x) * TPW;
+    const int64_t b = b0 + slot;
     const bool active = b < batch;
     const int64_t row = b * N;
+    float* lr = lds + slot * C::SLOT;
+    float* li = C::SPLIT ? lr : lr + TPW * C::SLOT;
 
     float vr[E], vi[E];
-    if constexpr (T == 1) {
+    if constexpr (C::F4IO) {
+        const int64_t rows_left = batch - b0;
+        const int valid = static_cast<int>(rows_left < TPW ? rows_left : TPW) * N;
+        const int64_t base = b0 * N;
+        if constexpr (C::SPLIT) {
+            stage_in<C>(xr, lds, base, valid, tid);
+            __syncthreads();
+            regs_from_natural<C>(vr, lr, t);
+            __syncthreads();
+            stage_in<C>(xi, lds, base, valid, tid);
+            __syncthreads();
+            regs_from_natural<C>(vi, lr, t);
+        } else {
+            stage_in<C>(xr, lds, base, valid, tid);
+            stage_in<C>(xi, lds + TPW * C::SLOT, base, valid, tid);
+            __syncthreads();
+            regs_from_natural<C>(vr, lr, t);
+            regs_from_natural<C>(vi, li, t);
+        }
+        // the next LDS writes (exchange or output staging) reuse these slots
+        __syncthreads();
+    } else if constexpr (T == 1) {
         // A whole transform per thread: natural-order vector loads; the bit
         // reversal is a renaming of registers.
         if (active) {
             if constexpr (N >= 4) {
-                const float4* pr = reinterpret_cast<const float4*>(xr + row);
-                const float4* pi = reinterpret_cast<const float4*>(xi + row);
 #pragma unroll
                 for (int c = 0; c < N / 4; ++c) {
-                    const float4 a = pr[c], z = pi[c];
-                    vr[rev_bits(4 * c + 0, M)] = a.x;
-                    vr[rev_bits(4 * c + 1, M)] = a.y;
-                    vr[rev_bits(4 * c + 2, M)] = a.z;
-                    vr[rev_bits(4 * c + 3, M)] = a.w;
-                    vi[rev_bits(4 * c + 0, M)] = z.x;
-                    vi[rev_bits(4 * c + 1, M)] = z.y;
-                    vi[rev_bits(4 * c + 2, M)] = z.z;
-                    vi[rev_bits(4 * c + 3, M)] = z.w;
+                    const v4f a = load4<NT>(xr + row + 4 * c), z = load4<NT>(xi + row + 4 * c);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        vr[rev_bits(4 * c + e, M)] = a[e];
+                        vi[rev_bits(4 * c + e, M)] = z[e];
+                    }
                 }
             } else {
 #pragma unroll
                 for (int n = 0; n < N; ++n) {
-                    vr[rev_bits(n, M)] = xr[row + n];
-                    vi[rev_bits(n, M)] = xi[row + n];
+                    vr[rev_bits(n, M)] = load1<NT>(xr + row + n);
+                    vi[rev_bits(n, M)] = load1<NT>(xi + row + n);
                 }
             }
         } else {
@@ -229,17 +362,49 @@ split_fft_lds_kernel(const float* xr, const float* xi, float* yr, float* yi, con
 #pragma unroll
         for (int u = 0; u < E; ++u) {
             const int64_t idx = row + tb + (rev_bits(u, RB) << LT);
-            vr[u] = active ? xr[idx] : 0.0f;
-            vi[u] = active ? xi[idx] : 0.0f;
+            vr[u] = active ? load1<NT>(xr + idx) : 0.0f;
+            vi[u] = active ? load1<NT>(xi + idx) : 0.0f;
         }
+    }
+
+    // Stage the twiddles of passes >= 1 (entries [E, N)) in LDS, entry idx
+    // at LDS element idx - E; the first LDS exchange's barrier orders these
+    // writes before their reads.
+    if constexpr (C::TW_LDS > 0) {
+        const v4f* src = reinterpret_cast<const v4f*>(tw + E);
+        for (int k = tid; k < C::TW_LDS / 2; k += C::THREADS)
+            lds_tw4[k] = src[k];
     }
 
     stages<E, LT, 0, Pass<M, RB, 0>::RP>(vr, vi, t, tw);
 
     if constexpr (NP > 1) {
-        float* lr = lds + slot * Sh::PADN;
-        float* li = SPLIT ? lr : lr + TPW * Sh::PADN;
-        later_passes<M, RB, 1, SPLIT, E>(vr, vi, lr, li, t, tw);
+        if constexpr (C::TW_LDS > 0)
+            later_passes<M, RB, 1, C::SPLIT, E, E>(vr, vi, lr, li, t, reinterpret_cast<const float2*>(lds_tw4));
+        else
+            later_passes<M, RB, 1, C::SPLIT, E, 0>(vr, vi, lr, li, t, tw);
+    }
+
+    if constexpr (C::F4IO) {
+        const int64_t rows_left = batch - b0;
+        const int valid = static_cast<int>(rows_left < TPW ? rows_left : TPW) * N;
+        const int64_t base = b0 * N;
+        if constexpr (C::SPLIT) {
+            regs_to_natural<C>(vr, lr, t);
+            __syncthreads();
+            stage_out<C>(yr, lds, base, valid, tid);
+            __syncthreads();
+            regs_to_natural<C>(vi, lr, t);
+            __syncthreads();
+            stage_out<C>(yi, lds, base, valid, tid);
+        } else {
+            regs_to_natural<C>(vr, lr, t);
+            regs_to_natural<C>(vi, li, t);
+            __syncthreads();
+            stage_out<C>(yr, lds, base, valid, tid);
+            stage_out<C>(yi, lds + TPW * C::SLOT, base, valid, tid);
+        }
+        return;
     }
 
     if (!active)
@@ -247,26 +412,24 @@ split_fft_lds_kernel(const float* xr, const float* xi, float* yr, float* yi, con
     using Last = Pass<M, RB, NP - 1>;
     if constexpr (T == 1) {
         if constexpr (N >= 4) {
-            float4* pr = reinterpret_cast<float4*>(yr + row);
-            float4* pi = reinterpret_cast<float4*>(yi + row);
 #pragma unroll
             for (int c = 0; c < N / 4; ++c) {
-                pr[c] = make_float4(vr[4 * c], vr[4 * c + 1], vr[4 * c + 2], vr[4 * c + 3]);
-                pi[c] = make_float4(vi[4 * c], vi[4 * c + 1], vi[4 * c + 2], vi[4 * c + 3]);
+                store4<NT>(yr + row + 4 * c, v4f{vr[4 * c], vr[4 * c + 1], vr[4 * c + 2], vr[4 * c + 3]});
+                store4<NT>(yi + row + 4 * c, v4f{vi[4 * c], vi[4 * c + 1], vi[4 * c + 2], vi[4 * c + 3]});
             }
         } else {
 #pragma unroll
             for (int n = 0; n < N; ++n) {
-                yr[row + n] = vr[n];
-                yi[row + n] = vi[n];
+                store1<NT>(yr + row + n, vr[n]);
+                store1<NT>(yi + row + n, vi[n]);
             }
         }
     } else {
 #pragma unroll
         for (int u = 0; u < E; ++u) {
             const int64_t idx = row + position<LT, Last::S, Last::RP>(t, u);
-            yr[idx] = vr[u];
-            yi[idx] = vi[u];
+            store1<NT>(yr + idx, vr[u]);
+            store1<NT>(yi + idx, vi[u]);
         }
     }
 }
@@ -294,46 +457,55 @@ hipError_t launch_len1(const float* xr, const float* xi, float* yr, float* yi, c
     return hipGetLastError();
 }
 
-template <int M, int RB, int TPW, bool SPLIT>
+template <class C>
 hipError_t launch_lds(const float* xr, const float* xi, float* yr, float* yi, const float2* tw, int64_t batch,
                       hipStream_t stream)
 {
-    using Sh = Shape<M, RB, TPW, SPLIT>;
-    const int64_t blocks = (batch + TPW - 1) / TPW;
+    const int64_t blocks = (batch + C::TPW - 1) / C::TPW;
     if (blocks > INT_MAX)
         return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((split_fft_lds_kernel<M, RB, TPW, SPLIT>), dim3(static_cast<unsigned>(blocks)),
-                       dim3(Sh::THREADS), 0, stream, xr, xi, yr, yi, tw, batch);
+    hipLaunchKernelGGL(split_fft_lds_kernel<C>, dim3(static_cast<unsigned>(blocks)), dim3(C::THREADS), 0, stream,
+                       xr, xi, yr, yi, tw, batch);
     return hipGetLastError();
 }
 
-#define SDFT_V(M, RB, TPW, SPLIT)                                                                              \
-    Variant                                                                                                    \
-    {                                                                                                          \
-        M, RB, TPW, Shape<M, RB, TPW, SPLIT>::THREADS,                                                         \
-            static_cast<int>(sizeof(float)) * Shape<M, RB, TPW, SPLIT>::LDS_WORDS, &launch_lds<M, RB, TPW, SPLIT> \
-    }
+template <class C>
+constexpr Variant make_variant()
+{
+    return Variant{C::M,  C::RB,  C::TPW, C::THREADS, C::LDS_BYTES, C::SPLIT,
+                   C::NT, C::TWL, C::WPE, C::F4IO,    &launch_lds<C>};
+}
 
 // Compiled schedules per length; the first entry of each list is the default.
-const Variant kV0[] = {Variant{0, 0, 256, 256, 0, &launch_len1}};
-const Variant kV1[] = {SDFT_V(1, 1, 256, false)};
-const Variant kV2[] = {SDFT_V(2, 2, 256, false)};
-const Variant kV3[] = {SDFT_V(3, 3, 256, false)};
-const Variant kV4[] = {SDFT_V(4, 4, 256, false), SDFT_V(4, 4, 64, false)};
-const Variant kV5[] = {SDFT_V(5, 5, 128, false), SDFT_V(5, 4, 128, false)};
-const Variant kV6[] = {SDFT_V(6, 3, 32, false), SDFT_V(6, 4, 64, false)};
-const Variant kV7[] = {SDFT_V(7, 4, 32, false), SDFT_V(7, 4, 16, false)};
-const Variant kV8[] = {SDFT_V(8, 4, 16, false), SDFT_V(8, 4, 4, false)};
-const Variant kV9[] = {SDFT_V(9, 5, 16, false), SDFT_V(9, 4, 8, false)};
-const Variant kV10[] = {SDFT_V(10, 5, 8, false), SDFT_V(10, 5, 2, false), SDFT_V(10, 4, 4, false),
-                        SDFT_V(10, 5, 8, true)};
-const Variant kV11[] = {SDFT_V(11, 4, 2, false), SDFT_V(11, 5, 4, false)};
-const Variant kV12[] = {SDFT_V(12, 4, 1, false), SDFT_V(12, 5, 2, false)};
-const Variant kV13[] = {SDFT_V(13, 5, 1, false), SDFT_V(13, 4, 1, false)};
-const Variant kV14[] = {SDFT_V(14, 5, 1, false), SDFT_V(14, 5, 1, true)};
-const Variant kV15[] = {SDFT_V(15, 5, 1, true)};
+//                              M   RB  TPW  SPLIT  NT     TWL    WPE
+const Variant kV0[] = {Variant{0, 0, 256, 256, 0, false, false, false, 1, false, &launch_len1}};
+template <int M, int RB, int TPW, bool SPLIT, bool NT, bool TWL, int WPE, bool F4IO = false>
+constexpr Variant V()
+{
+    return make_variant<Cfg<M, RB, TPW, SPLIT, NT, TWL, WPE, F4IO>>();
+}
 
-#undef SDFT_V
+constexpr bool Y = true, _ = false;
+//                      M   RB TPW SPLIT NT TWL WPE F4IO
+const Variant kV1[] = {V<1, 1, 256, _, _, _, 1>()};
+const Variant kV2[] = {V<2, 2, 256, _, _, _, 1>()};
+const Variant kV3[] = {V<3, 3, 256, _, _, _, 1>()};
+const Variant kV4[] = {V<4, 4, 64, _, Y, _, 1, Y>(), V<4, 4, 64, _, _, _, 1, Y>(), V<4, 4, 64, _, _, _, 1>(),
+                       V<4, 4, 256, _, _, _, 1, Y>()};
+const Variant kV5[] = {V<5, 4, 64, _, Y, Y, 1, Y>(), V<5, 4, 64, _, _, Y, 1, Y>(), V<5, 5, 128, _, _, _, 1>()};
+const Variant kV6[] = {V<6, 4, 64, _, Y, Y, 1, Y>(), V<6, 4, 32, _, _, Y, 1, Y>(), V<6, 3, 32, _, _, _, 1>()};
+const Variant kV7[] = {V<7, 4, 16, _, Y, Y, 1, Y>(), V<7, 4, 16, _, _, Y, 1, Y>(), V<7, 4, 32, _, _, _, 1>()};
+const Variant kV8[] = {V<8, 4, 16, Y, Y, Y, 4, Y>(), V<8, 4, 16, _, Y, Y, 1, Y>(), V<8, 4, 16, _, _, _, 1>()};
+const Variant kV9[] = {V<9, 4, 8, Y, Y, Y, 4, Y>(), V<9, 4, 8, _, Y, Y, 1>(), V<9, 4, 8, _, Y, Y, 1, Y>()};
+const Variant kV10[] = {V<10, 4, 4, Y, Y, Y, 4>(),    V<10, 4, 4, Y, Y, Y, 4, Y>(), V<10, 4, 4, _, Y, Y, 4, Y>(),
+                        V<10, 5, 8, Y, Y, Y, 1, Y>(), V<10, 5, 8, Y, Y, Y, 1>(),    V<10, 4, 8, Y, Y, Y, 4, Y>(),
+                        V<10, 4, 2, Y, Y, _, 4>(),    V<10, 4, 1, Y, Y, _, 4>()};
+const Variant kV11[] = {V<11, 5, 4, Y, Y, Y, 1>(), V<11, 4, 2, Y, Y, Y, 4, Y>(), V<11, 5, 4, Y, Y, Y, 1, Y>()};
+const Variant kV12[] = {V<12, 5, 2, _, Y, _, 1>(), V<12, 5, 2, Y, Y, Y, 1>(), V<12, 4, 1, Y, Y, _, 4>(),
+                        V<12, 4, 2, Y, Y, _, 4>(),  V<12, 4, 1, Y, Y, Y, 4, Y>()};
+const Variant kV13[] = {V<13, 5, 1, _, Y, _, 1>(), V<13, 5, 1, Y, Y, _, 1, Y>()};
+const Variant kV14[] = {V<14, 5, 1, _, Y, _, 1>(), V<14, 5, 1, Y, Y, _, 1>()};
+const Variant kV15[] = {V<15, 5, 1, Y, Y, _, 1>()};
 
 struct VariantList {
     const Variant* v;

@@ -7,13 +7,18 @@
 namespace splitdft {
 
 // One compiled single-pass kernel: transforms of length 2^m, 2^rb elements per
-// thread, tpw transforms per workgroup.
+// thread, tpw transforms per workgroup, plus data-movement options.
 struct Variant {
     int m;
     int rb;
     int tpw;
     int threads;  // workgroup size = tpw * 2^(m - rb)
     int lds_bytes;
+    bool split;   // LDS exchange one plane at a time
+    bool nt;      // nontemporal streaming loads/stores
+    bool twl;     // twiddles of passes >= 1 staged in LDS
+    int wpe;      // occupancy hint (minimum waves per SIMD)
+    bool f4io;    // 16-byte global I/O staged through LDS
     hipError_t (*launch)(const float* xr, const float* xi, float* yr, float* yi,
                          const float2* tw, int64_t batch, hipStream_t stream);
 };

@@ -80,6 +80,8 @@ def test_calls_with_invalid_plan(L):
     assert L.split_dft_destroy(None) == 0
     assert L.split_dft_plan_info(bogus, None, None, None, None, None) == 9
     assert L.split_dft_workspace_bytes(None) == 0
+    b = ctypes.create_string_buffer(16)
+    assert L.split_dft_plan_describe(bogus, b, 16) == 9
 
 
 def test_status_strings(L):
