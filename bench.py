@@ -35,12 +35,11 @@ HBM_PEAK_GBS = 8000.0
 N, BATCH = 1024, 16384
 ROTATE_SETS = 4
 
-# HBM traffic of the forward length-1024 kernel from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE counters (KiB per dispatch), scaled by the counter/byte ratio of a
-# plain copy kernel.  Valid only for the kernel source it was measured on.
-TRAFFIC = {
-    # "sha256 of csrc/fft_lds.hip": bytes per launch
-}
+# HBM traffic of the forward length-1024 kernel: rocprofv3 FETCH_SIZE and
+# WRITE_SIZE per dispatch, scaled by what the same counters read for a plain
+# copy of known size.  The summary records the kernel source it was measured
+# on; for any other source the traffic is reported as null.
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "split_fft_n1024_b16384_hbm_traffic.md")
 
 
 def kernel_source_hash() -> str:
@@ -49,8 +48,29 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def cpu_baseline(xr, xi, gr, gi):
-    """Time the CPU oracle on the same step (forward + adjoint)."""
+def measured_traffic():
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if ":" in line:
+            k, v = line.strip().split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return int(float(fields["traffic_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(xr, xi, gr, gi, budget_s: float = 2.0):
+    """Time the CPU oracle (FP64 factorised transform, OpenMP over rows) on
+    the same step: forward of x and adjoint of g over all rows, repeated
+    until about ``budget_s`` seconds of wall time (times the thread count in
+    CPU time) have passed."""
     import numpy as np
 
     import oracle
@@ -59,24 +79,50 @@ def cpu_baseline(xr, xi, gr, gi):
     a, b = xr.numpy().astype(np.float64), xi.numpy().astype(np.float64)
     c, d = gr.numpy().astype(np.float64), gi.numpy().astype(np.float64)
     rows = a.shape[0]
-    # bound the sample to roughly 10-30 s of work
+    reps = 0
     t0 = time.perf_counter()
-    oracle.split_fft(a[:64], b[:64])
-    per_row = (time.perf_counter() - t0) / 64
-    sample = int(max(64, min(rows, 10.0 / max(per_row * 2, 1e-9))))
-    t0 = time.perf_counter()
-    oracle.split_fft(a[:sample], b[:sample])
-    # the adjoint through the plane swap: (C g_r - S g_i, S g_r + C g_i)
-    oracle.split_fft(d[:sample], c[:sample])
-    dt = time.perf_counter() - t0
-    nbytes = 2 * 16 * N * sample
+    while True:
+        oracle.split_fft(a, b)
+        # the adjoint through the plane swap: (C g_r - S g_i, S g_r + C g_i)
+        oracle.split_fft(d, c)
+        reps += 1
+        dt = time.perf_counter() - t0
+        if dt >= budget_s:
+            break
+    nbytes = 2 * 16 * N * rows * reps
     return {
-        "value": nbytes / dt / 1e9,
+        "value": round(nbytes / dt / 1e9, 3),
         "unit": "GB/s",
         "cores": int(threads),
         "kind": "oracle",
-        "sample": "%d of %d rows (N=%d), FP64 factorised forward + adjoint, %.2f s" % (sample, rows, N, dt),
+        "sample": "all %d rows (N=%d), FP64 factorised forward + adjoint, %d repetitions in %.2f s wall"
+                  % (rows, N, reps, dt),
     }
+
+
+def counters_run(reps: int = 5):
+    """Launch the forward length-1024 kernel and a plain device copy of the
+    same byte count (128 MiB read, 128 MiB written) ``reps`` times each, for
+    hardware-counter collection: the copy's FETCH_SIZE / WRITE_SIZE per
+    dispatch calibrate the counters against known bytes."""
+    import torch
+
+    from paper_2504_07264_amd import Plan, inputs
+
+    dev = torch.device("cuda", 0)
+    xr, xi = inputs.draw(inputs.HEADLINE_N1024)
+    xr, xi = xr.to(dev), xi.to(dev)
+    yr, yi = torch.empty_like(xr), torch.empty_like(xi)
+    src = torch.randn(2, N * BATCH, device=dev)
+    dst = torch.empty_like(src)
+    with Plan(N, BATCH) as plan:
+        for _ in range(reps):
+            plan.exec(xr, xi, yr, yi)
+            torch.cuda.synchronize()
+            dst.copy_(src)
+            torch.cuda.synchronize()
+        print(json.dumps({"counters_run": reps, "schedule": plan.describe(),
+                          "copy_bytes_each_way": src.numel() * 4}), flush=True)
 
 
 def main():
@@ -85,12 +131,18 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--counters", action="store_true",
+                    help="only launch the forward kernel and a calibration copy (for rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; the transforms are independent per row, "
               "so N GPUs would each run the same kernel on batch/N rows with no communication. "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+
+    if args.counters:
+        counters_run()
+        return
 
     import torch
 
@@ -144,9 +196,8 @@ def main():
     gbs = step_bytes / (ms_per_step * 1e-3) / 1e9
     flops = 2 * 5 * N * math.log2(N) * BATCH
     achieved = launch_bytes / (fwd_mean_ms * 1e-3) / 1e9
-    traffic = TRAFFIC.get(kernel_source_hash())
+    traffic = measured_traffic()
 
-    info = plan.info()
     out = {
         "metric": METRIC,
         "value": round(gbs, 2),
@@ -165,7 +216,7 @@ def main():
             "n": N,
             "batch": BATCH,
             "inputs": "FP32 planar N(0,1), seeds 1 (x) and 101 (upstream gradient)",
-            "schedule": "%d elements/thread, %d transforms/workgroup" % (info["ept"], info["tpw"]),
+            "schedule": plan.describe(),
             "rotating_buffer_sets": ROTATE_SETS,
         },
         "gflops_5nlogn": round(flops / (ms_per_step * 1e-3) / 1e9, 1),
