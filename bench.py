@@ -125,12 +125,58 @@ def counters_run(reps: int = 5):
                           "copy_bytes_each_way": src.numel() * 4}), flush=True)
 
 
+# executed 16x16x32 matrix-core instructions per length-256 transform (two
+# 16-point stages x two output planes x products per split mode)
+MFMA_PER_TRANSFORM = {"bf16x2": 2 * 2 * 3, "fp16x2": 2 * 2 * 3, "bf16x3": 2 * 2 * 6}
+MFMA_FLOPS = 2 * 16 * 16 * 32
+MFMA_PEAK_TFLOPS = 2500.0  # dense bf16 / fp16
+
+
+def mfma_vs_fp32(steps: int = 50, sets: int = 4):
+    """Forward N=256 x 65536 (uniform[-1, 1], seed 3) in FP32 and in the three
+    matrix-core split-precision modes: mean launch time from HIP events."""
+    import torch
+
+    from paper_2504_07264_amd import Plan, binding, inputs
+
+    w = inputs.PREC_N256
+    xr, xi = inputs.draw(w)
+    dev = torch.device("cuda", 0)
+    bufs = [(xr.to(dev), xi.to(dev), torch.empty_like(xr, device=dev), torch.empty_like(xi, device=dev))
+            for _ in range(sets)]
+    stream = torch.cuda.current_stream(dev)
+    out = {"workload": "split_fft_n256_b65536_uniform forward", "n": w.n, "batch": w.batch}
+    nbytes = 16 * w.n * w.batch
+    for name in ("fp32", "bf16x2", "fp16x2", "bf16x3"):
+        with Plan(w.n, w.batch, binding.PRECISIONS[name]) as plan:
+            for k in range(5):
+                a, b, c, d = bufs[k % sets]
+                plan.exec(a, b, c, d)
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(steps)]
+            for k in range(steps):
+                a, b, c, d = bufs[k % sets]
+                ev[k][0].record(stream)
+                plan.exec(a, b, c, d)
+                ev[k][1].record(stream)
+            torch.cuda.synchronize()
+            us = sum(x.elapsed_time(y) for x, y in ev) / steps * 1e3
+            rec = {"us": round(us, 2), "GBps": round(nbytes / us / 1e3, 1), "schedule": plan.describe()}
+            if name in MFMA_PER_TRANSFORM:
+                tflops = MFMA_PER_TRANSFORM[name] * MFMA_FLOPS * w.batch / us / 1e6
+                rec["mfma_tflops"] = round(tflops, 1)
+                rec["mfma_utilisation"] = round(tflops / MFMA_PEAK_TFLOPS, 4)
+            out[name] = rec
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mfma", action="store_true", help="skip the matrix-core comparison")
     ap.add_argument("--counters", action="store_true",
                     help="only launch the forward kernel and a calibration copy (for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -233,6 +279,10 @@ def main():
         },
         "device": torch.cuda.get_device_name(dev),
     }
+    if not args.no_mfma:
+        del sets
+        torch.cuda.empty_cache()
+        out["mfma_vs_fp32"] = mfma_vs_fp32()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(xr, xi, gr, gi)
     plan.close()

@@ -61,8 +61,20 @@ typedef enum {
     SPLIT_DFT_ERR_INVALID_PLAN = 9    /* NULL, destroyed or foreign plan    */
 } split_dft_status;
 
-/* Plan flags (precision of the arithmetic). */
-#define SPLIT_DFT_FP32 0u /* FP32 throughout (the default) */
+/* Plan flags, bits 0-7: precision of the arithmetic. */
+#define SPLIT_DFT_FP32 0u /* FP32 throughout (the default); bit-exact eq. (6) */
+/* Matrix-core modes (n = 256 only): the two 16-point sub-DFT stages of the
+ * factorisation (stages 1-4 and 5-8 of eq. (6), grouped) run as dense
+ * contractions with the block matrix of eq. (5) at N = 16 on the MI355X
+ * matrix cores, operands split into low-precision parts, FP32 accumulation;
+ * the twiddle between them is FP32.  Results are approximations of the DFT
+ * (not bit-exact): */
+#define SPLIT_DFT_BF16X2 1u /* bf16 hi+lo, 3 products: rel. error ~4e-6         */
+#define SPLIT_DFT_FP16X2 2u /* fp16 hi+lo (lo scaled by 2^11), 3 products;
+                               needs |x| * 16 < 65504                            */
+#define SPLIT_DFT_BF16X3 3u /* bf16 hi+mid+lo, 6 products                       */
+/* Bits 8-15: 0 = default kernel schedule, k = compiled FP32 schedule k-1
+ * (used by tuning); bits 16-31 must be 0. */
 
 /* Largest supported log2 N. */
 #define SPLIT_DFT_MAX_LOG2N 16

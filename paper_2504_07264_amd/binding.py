@@ -27,6 +27,10 @@ STATUS_NAMES = {
     5: "ALIASING", 6: "UNSUPPORTED", 7: "OUT_OF_MEMORY", 8: "HIP", 9: "INVALID_PLAN",
 }
 FP32 = 0
+BF16X2 = 1
+FP16X2 = 2
+BF16X3 = 3
+PRECISIONS = {"fp32": FP32, "bf16x2": BF16X2, "fp16x2": FP16X2, "bf16x3": BF16X3}
 MAX_LOG2N = 16
 
 EXPORTED = (

@@ -20,7 +20,9 @@ struct split_dft_plan_s {
     uint32_t flags;
     int device;
     float2* d_tw;  // 2^m entries: (cos, sin) of omega^(i,q) at 2^(i-1)+q
-    const splitdft::Variant* variant;
+    const splitdft::Variant* variant;  // FP32 schedule (mode == kModeFP32)
+    int mode;                          // precision mode (plan flags & 0xff)
+    float* d_mfma;  // matrix-core modes: constant operands, then 256 (cos, sin) pairs
 };
 
 namespace {
@@ -97,11 +99,16 @@ split_dft_status run(split_dft_plan_t p, const float* xr, const float* xi, float
 {
     if (!p || !plan_is_live(p))
         return fail(SPLIT_DFT_ERR_INVALID_PLAN, "plan is NULL, destroyed or not created by split_dft_plan");
-    const split_dft_status st = validate_io(p, xr, xi, yr, yi);
-    if (st != SPLIT_DFT_OK)
-        return st;
+    const split_dft_status vs = validate_io(p, xr, xi, yr, yi);
+    if (vs != SPLIT_DFT_OK)
+        return vs;
+    const hipStream_t st = static_cast<hipStream_t>(stream);
     const hipError_t e =
-        p->variant->launch(xr, xi, yr, yi, p->d_tw, p->batch, static_cast<hipStream_t>(stream));
+        p->mode == splitdft::kModeFP32
+            ? p->variant->launch(xr, xi, yr, yi, p->d_tw, p->batch, st)
+            : splitdft::launch_mfma(p->mode, p->m, xr, xi, yr, yi, p->d_mfma,
+                                    reinterpret_cast<const float2*>(p->d_mfma + splitdft::kMfmaConstFloats),
+                                    p->batch, st);
     if (e != hipSuccess)
         return fail_hip(e, "kernel launch");
     return SPLIT_DFT_OK;
@@ -124,8 +131,11 @@ split_dft_status split_dft_plan(split_dft_plan_t* out, int64_t n, int64_t batch,
         return fail(SPLIT_DFT_ERR_INVALID_BATCH, "n * batch * 4 bytes overflows int64");
     const uint32_t precision = flags & 0xffu;
     const uint32_t vsel = (flags >> 8) & 0xffu;  // 0 = default schedule, k = compiled schedule k-1
-    if (precision != SPLIT_DFT_FP32 || (flags >> 16) != 0)
+    if (precision > SPLIT_DFT_BF16X3 || (flags >> 16) != 0)
         return fail(SPLIT_DFT_ERR_UNSUPPORTED, "unsupported flags " + std::to_string(flags));
+    const int mode = static_cast<int>(precision);
+    if (mode != splitdft::kModeFP32 && (m != 8 || vsel != 0))
+        return fail(SPLIT_DFT_ERR_UNSUPPORTED, "matrix-core precision modes support n = 256 only");
 
     int count = 0;
     const splitdft::Variant* list = splitdft::variants_for(m, &count);
@@ -163,8 +173,26 @@ split_dft_status split_dft_plan(split_dft_plan_t* out, int64_t n, int64_t batch,
         (void)hipFree(d_tw);
         return fail_hip(e, "hipMemcpy of the twiddle table");
     }
-    auto* p = new (std::nothrow) split_dft_plan_s{n, batch, m, flags, dev, d_tw, v};
+    float* d_mfma = nullptr;
+    if (mode != splitdft::kModeFP32) {
+        std::vector<float> tab(splitdft::kMfmaConstFloats + 2 * 256);
+        splitdft::build_mfma256_constants(mode, tab.data());
+        splitdft::build_tw256(tab.data() + splitdft::kMfmaConstFloats);
+        e = hipMalloc(&d_mfma, sizeof(float) * tab.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(d_mfma, tab.data(), sizeof(float) * tab.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            if (d_mfma)
+                (void)hipFree(d_mfma);
+            (void)hipFree(d_tw);
+            return e == hipErrorOutOfMemory ? fail(SPLIT_DFT_ERR_OUT_OF_MEMORY, "hipMalloc of the matrix-core tables")
+                                            : fail_hip(e, "matrix-core tables");
+        }
+    }
+    auto* p = new (std::nothrow) split_dft_plan_s{n, batch, m, flags, dev, d_tw, v, mode, d_mfma};
     if (!p) {
+        if (d_mfma)
+            (void)hipFree(d_mfma);
         (void)hipFree(d_tw);
         return fail(SPLIT_DFT_ERR_OUT_OF_MEMORY, "host allocation of the plan failed");
     }
@@ -210,7 +238,12 @@ split_dft_status split_dft_destroy(split_dft_plan_t plan)
     const bool switch_dev = hipGetDevice(&cur) == hipSuccess && cur != plan->device;
     if (switch_dev)
         (void)hipSetDevice(plan->device);
-    const hipError_t e = hipFree(plan->d_tw);
+    hipError_t e = hipFree(plan->d_tw);
+    if (plan->d_mfma) {
+        const hipError_t e2 = hipFree(plan->d_mfma);
+        if (e == hipSuccess)
+            e = e2;
+    }
     if (switch_dev)
         (void)hipSetDevice(cur);
     delete plan;
@@ -249,6 +282,11 @@ split_dft_status split_dft_plan_describe(split_dft_plan_t plan, char* buf, size_
         return fail(SPLIT_DFT_ERR_INVALID_PLAN, "plan is NULL, destroyed or not created by split_dft_plan");
     if (!buf || len == 0)
         return fail(SPLIT_DFT_ERR_NULL_POINTER, "buf is NULL or len is 0");
+    if (plan->mode != splitdft::kModeFP32) {
+        static const char* names[] = {"fp32", "bf16x2", "fp16x2", "bf16x3"};
+        std::snprintf(buf, len, "mfma16x16x32 %s two 16-point contractions, 4 waves/workgroup", names[plan->mode]);
+        return SPLIT_DFT_OK;
+    }
     const splitdft::Variant* v = plan->variant;
     std::snprintf(buf, len, "ept=%d tpw=%d threads=%d lds=%d split=%d nt=%d twl=%d wpe=%d f4io=%d", 1 << v->rb,
                   v->tpw, v->threads, v->lds_bytes, v->split ? 1 : 0, v->nt ? 1 : 0, v->twl ? 1 : 0, v->wpe,

@@ -32,4 +32,27 @@ const Variant* default_variant(int m, int64_t batch);
 // Host twiddle table: entry 2^(i-1)+q = (cos, sin) of 2*pi*q/2^i, FP32.
 void build_twiddles_f32(int m, float* c, float* s);
 
+// cos and sin of 2*pi*num/2^lg in FP64, exact at multiples of pi/4.
+void turn_fraction_f64(int64_t num, int lg, double* c, double* s);
+
+// Split-precision matrix-core modes (plan flag values).
+constexpr int kModeFP32 = 0;
+constexpr int kModeBF16X2 = 1;
+constexpr int kModeFP16X2 = 2;
+constexpr int kModeBF16X3 = 3;
+
+// Words of the per-mode constant table of the length-256 matrix-core kernel.
+constexpr int kMfmaConstFloats = 4 * 64 * 8 * 3;
+
+// Host: constant operands of the length-256 matrix-core kernel for `mode`,
+// split from FP64 into parts exactly representable in the low-precision type.
+void build_mfma256_constants(int mode, float* out);
+
+// Host: (cos, sin) of 2*pi*t/256 for t = 0..255 (exact at multiples of pi/4).
+void build_tw256(float* cs);
+
+// Launch the matrix-core kernel (only length 2^8 is supported).
+hipError_t launch_mfma(int mode, int m, const float* xr, const float* xi, float* yr, float* yi, const float* consts,
+                       const float2* tw256, int64_t batch, hipStream_t stream);
+
 }  // namespace splitdft

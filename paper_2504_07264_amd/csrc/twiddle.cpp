@@ -29,6 +29,7 @@ CosSin turn_fraction(int64_t num, int lg)
 {
     const int64_t den = int64_t{1} << lg;
     // 4*num = quarters * den + rem, with rem moved into (-den/2, den/2].
+    num &= den - 1;  // whole turns
     int64_t quarters = (num * 4) / den;
     int64_t rem = (num * 4) - quarters * den;
     if (rem * 2 > den) {
@@ -60,6 +61,13 @@ CosSin turn_fraction(int64_t num, int lg)
 }
 
 }  // namespace
+
+void turn_fraction_f64(int64_t num, int lg, double* c, double* s)
+{
+    const CosSin v = turn_fraction(num, lg);
+    *c = v.c;
+    *s = v.s;
+}
 
 void build_twiddles_f32(int m, float* c, float* s)
 {

@@ -60,6 +60,13 @@ def test_plan_rejects_unknown_flags(L):
     assert _plan(L, 16, 4, binding.variant_flag(200))[0] == 6
 
 
+@pytest.mark.parametrize("n", [16, 128, 512, 1 << 16])
+@pytest.mark.parametrize("mode", [binding.BF16X2, binding.FP16X2, binding.BF16X3])
+def test_matrix_core_modes_need_n256(L, n, mode):
+    st, h = _plan(L, n, 4, mode)
+    assert st == 6 and h.value is None
+
+
 def test_plan_null_out(L):
     assert L.split_dft_plan(None, 16, 1, 0) == 3
 
