@@ -111,6 +111,26 @@ __device__ __forceinline__ void stages(float (&vr)[E], float (&vi)[E], int t, co
     }
 }
 
+// Orders a wave's LDS writes before its later LDS reads by other lanes of the
+// same wave (LDS operations of one wave complete in order).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Synchronisation of an LDS exchange among the T threads of one transform:
+// a transform of at most 64 threads lies within one wave.
+template <int T>
+__device__ __forceinline__ void xsync()
+{
+    if constexpr (T <= 64)
+        wave_lds_sync();
+    else
+        __syncthreads();
+}
+
 template <int M, int RB, int P>
 struct Pass {
     static constexpr int S = P * RB;
@@ -144,20 +164,20 @@ __device__ __forceinline__ void later_passes(float (&vr)[E], float (&vi)[E], flo
         using Cur = Pass<M, RB, P>;
         if constexpr (SPLIT) {  // one plane at a time through the same LDS
             lds_put<E, LT, Prev::S, Prev::RP, Cur::S, Cur::RP>(vr, lr, t);
-            __syncthreads();
+            xsync<(1 << (M - RB))>();
             lds_get<E, LT, Cur::S, Cur::RP>(vr, lr, t);
-            __syncthreads();
+            xsync<(1 << (M - RB))>();
             lds_put<E, LT, Prev::S, Prev::RP, Cur::S, Cur::RP>(vi, lr, t);
-            __syncthreads();
+            xsync<(1 << (M - RB))>();
             lds_get<E, LT, Cur::S, Cur::RP>(vi, lr, t);
-            __syncthreads();
+            xsync<(1 << (M - RB))>();
         } else {
             lds_put<E, LT, Prev::S, Prev::RP, Cur::S, Cur::RP>(vr, lr, t);
             lds_put<E, LT, Prev::S, Prev::RP, Cur::S, Cur::RP>(vi, li, t);
-            __syncthreads();
+            xsync<(1 << (M - RB))>();
             lds_get<E, LT, Cur::S, Cur::RP>(vr, lr, t);
             lds_get<E, LT, Cur::S, Cur::RP>(vi, li, t);
-            __syncthreads();
+            xsync<(1 << (M - RB))>();
         }
         stages<E, LT, Cur::S, Cur::RP, TWOFF>(vr, vi, t, tw);
         later_passes<M, RB, P + 1, SPLIT, E, TWOFF>(vr, vi, lr, li, t, tw);
@@ -233,14 +253,16 @@ __device__ __forceinline__ void store4(float* p, v4f v)
         *reinterpret_cast<v4f*>(p) = v;
 }
 
-// 16-byte loads of one plane of the workgroup's rows (valid floats only)
-// into LDS; float f of the block lands in slot f / N at lds_index(f mod N).
-template <class C>
-__device__ __forceinline__ void stage_in(const float* x, float* area, int64_t base, int valid, int tid)
+// 16-byte loads of one plane of a sync group's rows (valid floats only) into
+// LDS; float f of the group's block lands in slot f / N at lds_index(f mod N).
+// GT threads share the work (a wave when transforms fit one wave, else the
+// workgroup), so each group stages only the rows its own exchange syncs cover.
+template <class C, int GT>
+__device__ __forceinline__ void stage_in(const float* x, float* area, int64_t base, int valid, int gtid)
 {
 #pragma unroll
     for (int c = 0; c < C::E / 4; ++c) {
-        const int f = 4 * (tid + c * C::THREADS);
+        const int f = 4 * (gtid + c * GT);
         if (f < valid) {
             const v4f v = load4<C::NT>(x + base + f);
             float* d = area + (f >> C::M) * C::SLOT + lds_index(f & (C::N - 1));
@@ -253,12 +275,12 @@ __device__ __forceinline__ void stage_in(const float* x, float* area, int64_t ba
 }
 
 // The reverse of stage_in: LDS slots to 16-byte global stores.
-template <class C>
-__device__ __forceinline__ void stage_out(float* y, const float* area, int64_t base, int valid, int tid)
+template <class C, int GT>
+__device__ __forceinline__ void stage_out(float* y, const float* area, int64_t base, int valid, int gtid)
 {
 #pragma unroll
     for (int c = 0; c < C::E / 4; ++c) {
-        const int f = 4 * (tid + c * C::THREADS);
+        const int f = 4 * (gtid + c * GT);
         if (f < valid) {
             const float* s = area + (f >> C::M) * C::SLOT + lds_index(f & (C::N - 1));
             store4<C::NT>(y + base + f, v4f{s[0], s[1], s[2], s[3]});
@@ -306,29 +328,45 @@ split_fft_lds_kernel(const float* xr, const float* xi, float* yr, float* yi, con
     const int64_t row = b * N;
     float* lr = lds + slot * C::SLOT;
     float* li = C::SPLIT ? lr : lr + TPW * C::SLOT;
+    // sync group of the LDS exchanges: one wave when a transform fits in it
+    constexpr int GT = (T <= 64) ? (C::THREADS < 64 ? C::THREADS : 64) : C::THREADS;
+    constexpr int GSLOTS = GT / T;
+    const int gtid = tid & (GT - 1);
+    const int gslot0 = (tid / GT) * GSLOTS;
+
+    // Stage the twiddles of passes >= 1 (entries [E, N)) in LDS, entry idx
+    // at LDS element idx - E, before the data loads are issued, so that the
+    // barrier making them visible waits only for the table's own loads.
+    if constexpr (C::TW_LDS > 0) {
+        const v4f* src = reinterpret_cast<const v4f*>(tw + E);
+        for (int k = tid; k < C::TW_LDS / 2; k += C::THREADS)
+            lds_tw4[k] = src[k];
+        __syncthreads();
+    }
 
     float vr[E], vi[E];
     if constexpr (C::F4IO) {
-        const int64_t rows_left = batch - b0;
-        const int valid = static_cast<int>(rows_left < TPW ? rows_left : TPW) * N;
-        const int64_t base = b0 * N;
+        const int64_t rows_left = batch - (b0 + gslot0);
+        const int valid = static_cast<int>(rows_left < GSLOTS ? (rows_left > 0 ? rows_left : 0) : GSLOTS) * N;
+        const int64_t base = (b0 + gslot0) * N;
+        float* gr = lds + gslot0 * C::SLOT;
         if constexpr (C::SPLIT) {
-            stage_in<C>(xr, lds, base, valid, tid);
-            __syncthreads();
+            stage_in<C, GT>(xr, gr, base, valid, gtid);
+            xsync<T>();
             regs_from_natural<C>(vr, lr, t);
-            __syncthreads();
-            stage_in<C>(xi, lds, base, valid, tid);
-            __syncthreads();
+            xsync<T>();
+            stage_in<C, GT>(xi, gr, base, valid, gtid);
+            xsync<T>();
             regs_from_natural<C>(vi, lr, t);
         } else {
-            stage_in<C>(xr, lds, base, valid, tid);
-            stage_in<C>(xi, lds + TPW * C::SLOT, base, valid, tid);
-            __syncthreads();
+            stage_in<C, GT>(xr, gr, base, valid, gtid);
+            stage_in<C, GT>(xi, gr + TPW * C::SLOT, base, valid, gtid);
+            xsync<T>();
             regs_from_natural<C>(vr, lr, t);
             regs_from_natural<C>(vi, li, t);
         }
         // the next LDS writes (exchange or output staging) reuse these slots
-        __syncthreads();
+        xsync<T>();
     } else if constexpr (T == 1) {
         // A whole transform per thread: natural-order vector loads; the bit
         // reversal is a renaming of registers.
@@ -367,15 +405,6 @@ split_fft_lds_kernel(const float* xr, const float* xi, float* yr, float* yi, con
         }
     }
 
-    // Stage the twiddles of passes >= 1 (entries [E, N)) in LDS, entry idx
-    // at LDS element idx - E; the first LDS exchange's barrier orders these
-    // writes before their reads.
-    if constexpr (C::TW_LDS > 0) {
-        const v4f* src = reinterpret_cast<const v4f*>(tw + E);
-        for (int k = tid; k < C::TW_LDS / 2; k += C::THREADS)
-            lds_tw4[k] = src[k];
-    }
-
     stages<E, LT, 0, Pass<M, RB, 0>::RP>(vr, vi, t, tw);
 
     if constexpr (NP > 1) {
@@ -386,23 +415,24 @@ split_fft_lds_kernel(const float* xr, const float* xi, float* yr, float* yi, con
     }
 
     if constexpr (C::F4IO) {
-        const int64_t rows_left = batch - b0;
-        const int valid = static_cast<int>(rows_left < TPW ? rows_left : TPW) * N;
-        const int64_t base = b0 * N;
+        const int64_t rows_left = batch - (b0 + gslot0);
+        const int valid = static_cast<int>(rows_left < GSLOTS ? (rows_left > 0 ? rows_left : 0) : GSLOTS) * N;
+        const int64_t base = (b0 + gslot0) * N;
+        float* gr = lds + gslot0 * C::SLOT;
         if constexpr (C::SPLIT) {
             regs_to_natural<C>(vr, lr, t);
-            __syncthreads();
-            stage_out<C>(yr, lds, base, valid, tid);
-            __syncthreads();
+            xsync<T>();
+            stage_out<C, GT>(yr, gr, base, valid, gtid);
+            xsync<T>();
             regs_to_natural<C>(vi, lr, t);
-            __syncthreads();
-            stage_out<C>(yi, lds, base, valid, tid);
+            xsync<T>();
+            stage_out<C, GT>(yi, gr, base, valid, gtid);
         } else {
             regs_to_natural<C>(vr, lr, t);
             regs_to_natural<C>(vi, li, t);
-            __syncthreads();
-            stage_out<C>(yr, lds, base, valid, tid);
-            stage_out<C>(yi, lds + TPW * C::SLOT, base, valid, tid);
+            xsync<T>();
+            stage_out<C, GT>(yr, gr, base, valid, gtid);
+            stage_out<C, GT>(yi, gr + TPW * C::SLOT, base, valid, gtid);
         }
         return;
     }
@@ -495,11 +525,13 @@ const Variant kV4[] = {V<4, 4, 64, _, Y, _, 1, Y>(), V<4, 4, 64, _, _, _, 1, Y>(
 const Variant kV5[] = {V<5, 4, 64, _, Y, Y, 1, Y>(), V<5, 4, 64, _, _, Y, 1, Y>(), V<5, 5, 128, _, _, _, 1>()};
 const Variant kV6[] = {V<6, 4, 64, _, Y, Y, 1, Y>(), V<6, 4, 32, _, _, Y, 1, Y>(), V<6, 3, 32, _, _, _, 1>()};
 const Variant kV7[] = {V<7, 4, 16, _, Y, Y, 1, Y>(), V<7, 4, 16, _, _, Y, 1, Y>(), V<7, 4, 32, _, _, _, 1>()};
-const Variant kV8[] = {V<8, 4, 16, Y, Y, Y, 4, Y>(), V<8, 4, 16, _, Y, Y, 1, Y>(), V<8, 4, 16, _, _, _, 1>()};
-const Variant kV9[] = {V<9, 4, 8, Y, Y, Y, 4, Y>(), V<9, 4, 8, _, Y, Y, 1>(), V<9, 4, 8, _, Y, Y, 1, Y>()};
+const Variant kV8[] = {V<8, 4, 16, Y, Y, Y, 4, Y>(), V<8, 4, 16, _, Y, Y, 1, Y>(), V<8, 4, 16, _, _, _, 1>(),
+                       V<8, 4, 32, Y, Y, Y, 4, Y>()};
+const Variant kV9[] = {V<9, 4, 8, Y, Y, Y, 4, Y>(), V<9, 4, 8, _, Y, Y, 1>(), V<9, 4, 8, _, Y, Y, 1, Y>(),
+                       V<9, 4, 16, Y, Y, Y, 4, Y>()};
 const Variant kV10[] = {V<10, 4, 4, Y, Y, Y, 4>(),    V<10, 4, 4, Y, Y, Y, 4, Y>(), V<10, 4, 4, _, Y, Y, 4, Y>(),
                         V<10, 5, 8, Y, Y, Y, 1, Y>(), V<10, 5, 8, Y, Y, Y, 1>(),    V<10, 4, 8, Y, Y, Y, 4, Y>(),
-                        V<10, 4, 2, Y, Y, _, 4>(),    V<10, 4, 1, Y, Y, _, 4>()};
+                        V<10, 4, 8, Y, Y, Y, 4>(),    V<10, 4, 16, Y, Y, Y, 4>(),   V<10, 4, 16, Y, Y, Y, 8>()};
 const Variant kV11[] = {V<11, 5, 4, Y, Y, Y, 1>(), V<11, 4, 2, Y, Y, Y, 4, Y>(), V<11, 5, 4, Y, Y, Y, 1, Y>()};
 const Variant kV12[] = {V<12, 5, 2, _, Y, _, 1>(), V<12, 5, 2, Y, Y, Y, 1>(), V<12, 4, 1, Y, Y, _, 4>(),
                         V<12, 4, 2, Y, Y, _, 4>(),  V<12, 4, 1, Y, Y, Y, 4, Y>()};
