@@ -108,11 +108,28 @@ split_dft_status split_dft_exec(split_dft_plan_t plan, const float *xr, const fl
 split_dft_status split_dft_adjoint(split_dft_plan_t plan, const float *gr, const float *gi,
                                    float *gxr, float *gxi, void *stream);
 
+/*
+ * As split_dft_exec / split_dft_adjoint, with a caller-owned workspace of at
+ * least split_dft_workspace_bytes(plan) bytes (device memory, 16-byte
+ * aligned, overlapping no data array).  Only two-pass plans (large n) use a
+ * workspace; for them the plain entry points use one owned by the plan, so
+ * concurrent calls on one two-pass plan from different streams must use these
+ * variants with separate workspaces.  workspace may be NULL (plan-owned).
+ */
+split_dft_status split_dft_exec_ws(split_dft_plan_t plan, const float *xr, const float *xi,
+                                   float *yr, float *yi, void *workspace, size_t workspace_bytes,
+                                   void *stream);
+split_dft_status split_dft_adjoint_ws(split_dft_plan_t plan, const float *gr, const float *gi,
+                                      float *gxr, float *gxi, void *workspace,
+                                      size_t workspace_bytes, void *stream);
+
 /* Release a plan and its device table.  NULL is accepted and ignored. */
 split_dft_status split_dft_destroy(split_dft_plan_t plan);
 
-/* Scratch bytes a plan needs beyond inputs and outputs (0 for every length
- * handled in a single pass). */
+/* Workspace bytes a plan needs beyond inputs and outputs: 0 for lengths
+ * handled in a single pass; for two-pass plans (n = 2^16 by default) the
+ * intermediate of one chunk of transforms, both planes (at most 64 MiB or one
+ * transform).  0 for a NULL or destroyed plan. */
 size_t split_dft_workspace_bytes(split_dft_plan_t plan);
 
 /* Plan properties: length, batch, log2 length and the kernel schedule chosen

@@ -34,7 +34,8 @@ PRECISIONS = {"fp32": FP32, "bf16x2": BF16X2, "fp16x2": FP16X2, "bf16x3": BF16X3
 MAX_LOG2N = 16
 
 EXPORTED = (
-    "split_dft_plan", "split_dft_exec", "split_dft_adjoint", "split_dft_destroy",
+    "split_dft_plan", "split_dft_exec", "split_dft_adjoint", "split_dft_exec_ws", "split_dft_adjoint_ws",
+    "split_dft_destroy",
     "split_dft_workspace_bytes", "split_dft_plan_info", "split_dft_plan_describe", "split_dft_twiddle_table",
     "split_dft_status_string", "split_dft_last_error",
 )
@@ -66,6 +67,10 @@ def lib() -> ctypes.CDLL:
         for name in ("split_dft_exec", "split_dft_adjoint"):
             fn = getattr(L, name)
             fn.argtypes = [vp, vp, vp, vp, vp, vp]
+            fn.restype = ci
+        for name in ("split_dft_exec_ws", "split_dft_adjoint_ws"):
+            fn = getattr(L, name)
+            fn.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
             fn.restype = ci
         L.split_dft_destroy.argtypes = [vp]
         L.split_dft_destroy.restype = ci

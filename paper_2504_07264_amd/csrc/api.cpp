@@ -23,11 +23,22 @@ struct split_dft_plan_s {
     const splitdft::Variant* variant;  // FP32 schedule (mode == kModeFP32)
     int mode;                          // precision mode (plan flags & 0xff)
     float* d_mfma;  // matrix-core modes: constant operands, then 256 (cos, sin) pairs
+    const splitdft::TwoPass* two;  // two-pass schedule (large lengths), else NULL
+    int64_t chunk;                 // transforms per two-pass chunk
+    float* d_ws;                   // plan-owned workspace: 2 planes x chunk x n floats
+    size_t ws_bytes;
 };
 
 namespace {
 
 thread_local std::string g_last_error;
+
+// Lengths from 2^14 up use the two-pass schedule by default (measured faster
+// than the single-workgroup kernels, which hold one transform per CU).
+constexpr int kTwoPassDefaultLog2N = 14;
+// Workspace per two-pass chunk (both planes): small enough to stay in the
+// Infinity Cache between the passes.
+constexpr int64_t kTwoPassChunkBytes = int64_t{64} << 20;
 
 std::mutex g_plans_mu;
 std::unordered_set<const split_dft_plan_s*>& live_plans()
@@ -76,6 +87,13 @@ bool overlaps(const void* a, const void* b, size_t bytes)
     return x < y + bytes && y < x + bytes;
 }
 
+// [a, a + abytes) and [b, b + bbytes) intersect
+bool ranges_overlap(const void* a, size_t abytes, const void* b, size_t bbytes)
+{
+    const auto x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + bbytes && y < x + abytes;
+}
+
 split_dft_status validate_io(const split_dft_plan_s* p, const float* xr, const float* xi, const float* yr,
                              const float* yi)
 {
@@ -95,7 +113,8 @@ split_dft_status validate_io(const split_dft_plan_s* p, const float* xr, const f
     return SPLIT_DFT_OK;
 }
 
-split_dft_status run(split_dft_plan_t p, const float* xr, const float* xi, float* yr, float* yi, void* stream)
+split_dft_status run(split_dft_plan_t p, const float* xr, const float* xi, float* yr, float* yi, void* ws,
+                     size_t ws_bytes, void* stream)
 {
     if (!p || !plan_is_live(p))
         return fail(SPLIT_DFT_ERR_INVALID_PLAN, "plan is NULL, destroyed or not created by split_dft_plan");
@@ -103,6 +122,34 @@ split_dft_status run(split_dft_plan_t p, const float* xr, const float* xi, float
     if (vs != SPLIT_DFT_OK)
         return vs;
     const hipStream_t st = static_cast<hipStream_t>(stream);
+    if (p->two) {
+        float* w = static_cast<float*>(ws);
+        if (!w) {
+            w = p->d_ws;
+        } else {
+            if (ws_bytes < p->ws_bytes)
+                return fail(SPLIT_DFT_ERR_INVALID_BATCH, "workspace smaller than split_dft_workspace_bytes");
+            if (reinterpret_cast<uintptr_t>(w) % 16 != 0)
+                return fail(SPLIT_DFT_ERR_MISALIGNED, "workspace must be 16-byte aligned");
+            const size_t bytes = static_cast<size_t>(p->n) * static_cast<size_t>(p->batch) * sizeof(float);
+            for (const void* q : {static_cast<const void*>(xr), static_cast<const void*>(xi),
+                                  static_cast<const void*>(yr), static_cast<const void*>(yi)})
+                if (ranges_overlap(w, p->ws_bytes, q, bytes))
+                    return fail(SPLIT_DFT_ERR_ALIASING, "workspace overlaps a data array");
+        }
+        float* wr = w;
+        float* wi = w + p->chunk * p->n;
+        for (int64_t s0 = 0; s0 < p->batch; s0 += p->chunk) {
+            const int64_t k = p->batch - s0 < p->chunk ? p->batch - s0 : p->chunk;
+            const int64_t off = s0 * p->n;
+            hipError_t e = p->two->pass1(xr + off, xi + off, wr, wi, p->d_tw, k, st);
+            if (e == hipSuccess)
+                e = p->two->pass2(wr, wi, yr + off, yi + off, p->d_tw, k, st);
+            if (e != hipSuccess)
+                return fail_hip(e, "two-pass kernel launch");
+        }
+        return SPLIT_DFT_OK;
+    }
     const hipError_t e =
         p->mode == splitdft::kModeFP32
             ? p->variant->launch(xr, xi, yr, yi, p->d_tw, p->batch, st)
@@ -137,14 +184,26 @@ split_dft_status split_dft_plan(split_dft_plan_t* out, int64_t n, int64_t batch,
     if (mode != splitdft::kModeFP32 && (m != 8 || vsel != 0))
         return fail(SPLIT_DFT_ERR_UNSUPPORTED, "matrix-core precision modes support n = 256 only");
 
-    int count = 0;
+    // schedules: the compiled single-pass variants, then the two-pass ones;
+    // selector 0 = the default for the length
+    int count = 0, count2 = 0;
     const splitdft::Variant* list = splitdft::variants_for(m, &count);
+    const splitdft::TwoPass* list2 = splitdft::two_pass_for(m, &count2);
     const splitdft::Variant* v = nullptr;
-    if (vsel == 0)
-        v = splitdft::default_variant(m, batch);
-    else if (static_cast<int>(vsel) <= count)
+    const splitdft::TwoPass* two = nullptr;
+    if (vsel == 0) {
+        if (mode != splitdft::kModeFP32 || count > 0)
+            v = splitdft::default_variant(m, batch);
+        if (m >= kTwoPassDefaultLog2N || !v)
+            two = count2 > 0 ? &list2[0] : nullptr;
+        if (two)
+            v = nullptr;
+    } else if (static_cast<int>(vsel) <= count) {
         v = &list[vsel - 1];
-    if (!v)
+    } else if (static_cast<int>(vsel) <= count + count2) {
+        two = &list2[vsel - 1 - count];
+    }
+    if (!v && !two)
         return fail(SPLIT_DFT_ERR_UNSUPPORTED,
                     "no compiled schedule for n = " + std::to_string(n) + " (selector " + std::to_string(vsel) + ")");
 
@@ -189,10 +248,31 @@ split_dft_status split_dft_plan(split_dft_plan_t* out, int64_t n, int64_t batch,
                                             : fail_hip(e, "matrix-core tables");
         }
     }
-    auto* p = new (std::nothrow) split_dft_plan_s{n, batch, m, flags, dev, d_tw, v, mode, d_mfma};
+    int64_t chunk = 0;
+    size_t ws_bytes = 0;
+    float* d_ws = nullptr;
+    if (two) {
+        int64_t chunk_bytes = kTwoPassChunkBytes;
+        if (const char* cb = std::getenv("SPLIT_DFT_CHUNK_MIB"))  // tuning override
+            if (std::atoll(cb) > 0)
+                chunk_bytes = std::atoll(cb) << 20;
+        chunk = chunk_bytes / (n * 2 * static_cast<int64_t>(sizeof(float)));
+        chunk = chunk < 1 ? 1 : (chunk > batch ? batch : chunk);
+        ws_bytes = static_cast<size_t>(chunk) * static_cast<size_t>(n) * 2 * sizeof(float);
+        e = hipMalloc(&d_ws, ws_bytes);
+        if (e != hipSuccess) {
+            (void)hipFree(d_tw);
+            return e == hipErrorOutOfMemory ? fail(SPLIT_DFT_ERR_OUT_OF_MEMORY, "hipMalloc of the workspace")
+                                            : fail_hip(e, "hipMalloc of the workspace");
+        }
+    }
+    auto* p = new (std::nothrow)
+        split_dft_plan_s{n, batch, m, flags, dev, d_tw, v, mode, d_mfma, two, chunk, d_ws, ws_bytes};
     if (!p) {
         if (d_mfma)
             (void)hipFree(d_mfma);
+        if (d_ws)
+            (void)hipFree(d_ws);
         (void)hipFree(d_tw);
         return fail(SPLIT_DFT_ERR_OUT_OF_MEMORY, "host allocation of the plan failed");
     }
@@ -200,12 +280,12 @@ split_dft_status split_dft_plan(split_dft_plan_t* out, int64_t n, int64_t batch,
         std::lock_guard<std::mutex> g(g_plans_mu);
         live_plans().insert(p);
     }
-    if (log_enabled())
-        std::fprintf(stderr,
-                     "[split_dft] plan n=%lld batch=%lld ept=%d tpw=%d threads=%d lds=%d split=%d nt=%d twl=%d "
-                     "wpe=%d\n",
-                     static_cast<long long>(n), static_cast<long long>(batch), 1 << v->rb, v->tpw, v->threads,
-                     v->lds_bytes, v->split, v->nt, v->twl, v->wpe);
+    if (log_enabled()) {
+        char desc[256];
+        split_dft_plan_describe(p, desc, sizeof(desc));
+        std::fprintf(stderr, "[split_dft] plan n=%lld batch=%lld %s\n", static_cast<long long>(n),
+                     static_cast<long long>(batch), desc);
+    }
     *out = p;
     return SPLIT_DFT_OK;
 }
@@ -213,7 +293,19 @@ split_dft_status split_dft_plan(split_dft_plan_t* out, int64_t n, int64_t batch,
 split_dft_status split_dft_exec(split_dft_plan_t plan, const float* xr, const float* xi, float* yr, float* yi,
                                 void* stream)
 {
-    return run(plan, xr, xi, yr, yi, stream);
+    return run(plan, xr, xi, yr, yi, nullptr, 0, stream);
+}
+
+split_dft_status split_dft_exec_ws(split_dft_plan_t plan, const float* xr, const float* xi, float* yr, float* yi,
+                                   void* workspace, size_t workspace_bytes, void* stream)
+{
+    return run(plan, xr, xi, yr, yi, workspace, workspace_bytes, stream);
+}
+
+split_dft_status split_dft_adjoint_ws(split_dft_plan_t plan, const float* gr, const float* gi, float* gxr,
+                                      float* gxi, void* workspace, size_t workspace_bytes, void* stream)
+{
+    return run(plan, gi, gr, gxi, gxr, workspace, workspace_bytes, stream);
 }
 
 split_dft_status split_dft_adjoint(split_dft_plan_t plan, const float* gr, const float* gi, float* gxr, float* gxi,
@@ -222,7 +314,7 @@ split_dft_status split_dft_adjoint(split_dft_plan_t plan, const float* gr, const
     // C gr - S gi = imaginary part and S gr + C gi = real part of the forward
     // transform of (gi, gr): the adjoint is the forward kernel with both
     // plane pairs exchanged.
-    return run(plan, gi, gr, gxi, gxr, stream);
+    return run(plan, gi, gr, gxi, gxr, nullptr, 0, stream);
 }
 
 split_dft_status split_dft_destroy(split_dft_plan_t plan)
@@ -239,6 +331,11 @@ split_dft_status split_dft_destroy(split_dft_plan_t plan)
     if (switch_dev)
         (void)hipSetDevice(plan->device);
     hipError_t e = hipFree(plan->d_tw);
+    if (plan->d_ws) {
+        const hipError_t e2 = hipFree(plan->d_ws);
+        if (e == hipSuccess)
+            e = e2;
+    }
     if (plan->d_mfma) {
         const hipError_t e2 = hipFree(plan->d_mfma);
         if (e == hipSuccess)
@@ -254,8 +351,9 @@ split_dft_status split_dft_destroy(split_dft_plan_t plan)
 
 size_t split_dft_workspace_bytes(split_dft_plan_t plan)
 {
-    (void)plan;
-    return 0;
+    if (!plan || !plan_is_live(plan))
+        return 0;
+    return plan->ws_bytes;
 }
 
 split_dft_status split_dft_plan_info(split_dft_plan_t plan, int64_t* n, int64_t* batch, int* log2n, int* ept,
@@ -270,9 +368,9 @@ split_dft_status split_dft_plan_info(split_dft_plan_t plan, int64_t* n, int64_t*
     if (log2n)
         *log2n = plan->m;
     if (ept)
-        *ept = 1 << plan->variant->rb;
+        *ept = plan->variant ? 1 << plan->variant->rb : 16;
     if (tpw)
-        *tpw = plan->variant->tpw;
+        *tpw = plan->variant ? plan->variant->tpw : 0;
     return SPLIT_DFT_OK;
 }
 
@@ -285,6 +383,15 @@ split_dft_status split_dft_plan_describe(split_dft_plan_t plan, char* buf, size_
     if (plan->mode != splitdft::kModeFP32) {
         static const char* names[] = {"fp32", "bf16x2", "fp16x2", "bf16x3"};
         std::snprintf(buf, len, "mfma16x16x32 %s two 16-point contractions, 4 waves/workgroup", names[plan->mode]);
+        return SPLIT_DFT_OK;
+    }
+    if (plan->two) {
+        const splitdft::TwoPass* t = plan->two;
+        std::snprintf(buf, len,
+                      "two-pass a=%d: pass1 %d blocks/wg %d threads lds=%d, pass2 %d columns/wg %d threads lds=%d, "
+                      "chunk=%lld",
+                      t->a, t->c1, t->threads1, t->lds1, t->c2, t->threads2, t->lds2,
+                      static_cast<long long>(plan->chunk));
         return SPLIT_DFT_OK;
     }
     const splitdft::Variant* v = plan->variant;

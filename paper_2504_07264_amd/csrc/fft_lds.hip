@@ -34,155 +34,12 @@
 // negate) are applied as such, which gives the same values as the general
 // form with the table's exact 1 and 0.  The results therefore equal, bit for
 // bit, the factors of eq. (6) applied one after the other in FP32.
-#include "internal.h"
+#include "fft_device.h"
 
 #include <climits>
 
 namespace splitdft {
 namespace {
-
-__device__ __forceinline__ int rev_bits(int x, int bits)
-{
-    return bits == 0 ? 0 : static_cast<int>(__builtin_bitreverse32(static_cast<unsigned>(x)) >> (32 - bits));
-}
-
-// LDS word of in-transform position j: one pad word after every 32 words, so
-// that the strided accesses of a pass transition spread over the banks.
-__host__ __device__ constexpr int lds_index(int j) { return j + (j >> 5); }
-
-template <int LT, int S, int RP>
-__device__ __forceinline__ int position(int t, int u)
-{
-    const int g = u >> RP;
-    const int uu = u & ((1 << RP) - 1);
-    const int o = t + (g << LT);
-    return (o & ((1 << S) - 1)) + (uu << S) + ((o >> S) << (S + RP));
-}
-
-// (ar, ai) <- omega (ar, ai), omega = [[c, s], [-s, c]].
-__device__ __forceinline__ void rotate(float& ar, float& ai, float c, float s)
-{
-    const float tr = __builtin_fmaf(c, ar, s * ai);
-    const float ti = __builtin_fmaf(c, ai, -(s * ar));
-    ar = tr;
-    ai = ti;
-}
-
-// Stages S+1 .. S+RP of eq. (6) on the E registers of one thread.  For S > 0
-// the twiddle of table entry idx is read at tw[idx - TWOFF] (TWOFF > 0 when
-// only the upper part of the table is staged).
-template <int E, int LT, int S, int RP, int TWOFF = 0>
-__device__ __forceinline__ void stages(float (&vr)[E], float (&vi)[E], int t, const float2* __restrict__ tw)
-{
-#pragma unroll
-    for (int k = 1; k <= RP; ++k) {
-        const int half = 1 << (k - 1);
-#pragma unroll
-        for (int u = 0; u < E; ++u) {
-            if (u & half)
-                continue;
-            const int v = u + half;
-            float ar = vr[v], ai = vi[v];
-            if constexpr (S == 0) {
-                const int q = u & (half - 1);
-                if (q == 0) {
-                    // omega^(k,0) = I
-                } else if (2 * q == half) {
-                    // omega at angle pi/2 = [[0, 1], [-1, 0]]
-                    const float tr = ai;
-                    ai = -ar;
-                    ar = tr;
-                } else {
-                    const float2 w = tw[half + q];
-                    rotate(ar, ai, w.x, w.y);
-                }
-            } else {
-                const int o = t + ((u >> RP) << LT);
-                const int q = (o & ((1 << S) - 1)) + ((u & (half - 1)) << S);
-                const float2 w = tw[(1 << (S + k - 1)) - TWOFF + q];
-                rotate(ar, ai, w.x, w.y);
-            }
-            const float ur = vr[u], ui = vi[u];
-            vr[u] = ur + ar;
-            vi[u] = ui + ai;
-            vr[v] = ur - ar;
-            vi[v] = ui - ai;
-        }
-    }
-}
-
-// Orders a wave's LDS writes before its later LDS reads by other lanes of the
-// same wave (LDS operations of one wave complete in order).
-__device__ __forceinline__ void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Synchronisation of an LDS exchange among the T threads of one transform:
-// a transform of at most 64 threads lies within one wave.
-template <int T>
-__device__ __forceinline__ void xsync()
-{
-    if constexpr (T <= 64)
-        wave_lds_sync();
-    else
-        __syncthreads();
-}
-
-template <int M, int RB, int P>
-struct Pass {
-    static constexpr int S = P * RB;
-    static constexpr int RP = (S + RB <= M) ? RB : (M - S);
-};
-
-template <int E, int LT, int S0, int RP0, int S1, int RP1>
-__device__ __forceinline__ void lds_put(const float (&v)[E], float* lds, int t)
-{
-#pragma unroll
-    for (int u = 0; u < E; ++u)
-        lds[lds_index(position<LT, S0, RP0>(t, u))] = v[u];
-}
-
-template <int E, int LT, int S1, int RP1>
-__device__ __forceinline__ void lds_get(float (&v)[E], const float* lds, int t)
-{
-#pragma unroll
-    for (int u = 0; u < E; ++u)
-        v[u] = lds[lds_index(position<LT, S1, RP1>(t, u))];
-}
-
-// Passes P, P+1, ... : exchange through LDS, then the pass's stages.
-template <int M, int RB, int P, bool SPLIT, int E, int TWOFF>
-__device__ __forceinline__ void later_passes(float (&vr)[E], float (&vi)[E], float* lr, float* li, int t,
-                                             const float2* __restrict__ tw)
-{
-    if constexpr (P * RB < M) {
-        constexpr int LT = M - RB;
-        using Prev = Pass<M, RB, P - 1>;
-        using Cur = Pass<M, RB, P>;
-        if constexpr (SPLIT) {  // one plane at a time through the same LDS
-            lds_put<E, LT, Prev::S, Prev::RP, Cur::S, Cur::RP>(vr, lr, t);
-            xsync<(1 << (M - RB))>();
-            lds_get<E, LT, Cur::S, Cur::RP>(vr, lr, t);
-            xsync<(1 << (M - RB))>();
-            lds_put<E, LT, Prev::S, Prev::RP, Cur::S, Cur::RP>(vi, lr, t);
-            xsync<(1 << (M - RB))>();
-            lds_get<E, LT, Cur::S, Cur::RP>(vi, lr, t);
-            xsync<(1 << (M - RB))>();
-        } else {
-            lds_put<E, LT, Prev::S, Prev::RP, Cur::S, Cur::RP>(vr, lr, t);
-            lds_put<E, LT, Prev::S, Prev::RP, Cur::S, Cur::RP>(vi, li, t);
-            xsync<(1 << (M - RB))>();
-            lds_get<E, LT, Cur::S, Cur::RP>(vr, lr, t);
-            lds_get<E, LT, Cur::S, Cur::RP>(vi, li, t);
-            xsync<(1 << (M - RB))>();
-        }
-        stages<E, LT, Cur::S, Cur::RP, TWOFF>(vr, vi, t, tw);
-        later_passes<M, RB, P + 1, SPLIT, E, TWOFF>(vr, vi, lr, li, t, tw);
-    }
-}
 
 // Compile-time schedule of one kernel instance.
 //   M      log2 of the transform length
@@ -214,44 +71,6 @@ struct Cfg {
     static constexpr int LDS_BYTES = 4 * XCH_WORDS + 8 * TW_LDS;
     static_assert(!F4IO || E >= 4, "16-byte I/O needs at least 4 elements per thread");
 };
-
-typedef float v4f __attribute__((ext_vector_type(4)));
-
-template <bool NT>
-__device__ __forceinline__ float load1(const float* p)
-{
-    if constexpr (NT)
-        return __builtin_nontemporal_load(p);
-    else
-        return *p;
-}
-
-template <bool NT>
-__device__ __forceinline__ void store1(float* p, float v)
-{
-    if constexpr (NT)
-        __builtin_nontemporal_store(v, p);
-    else
-        *p = v;
-}
-
-template <bool NT>
-__device__ __forceinline__ v4f load4(const float* p)
-{
-    if constexpr (NT)
-        return __builtin_nontemporal_load(reinterpret_cast<const v4f*>(p));
-    else
-        return *reinterpret_cast<const v4f*>(p);
-}
-
-template <bool NT>
-__device__ __forceinline__ void store4(float* p, v4f v)
-{
-    if constexpr (NT)
-        __builtin_nontemporal_store(v, reinterpret_cast<v4f*>(p));
-    else
-        *reinterpret_cast<v4f*>(p) = v;
-}
 
 // 16-byte loads of one plane of a sync group's rows (valid floats only) into
 // LDS; float f of the group's block lands in slot f / N at lds_index(f mod N).

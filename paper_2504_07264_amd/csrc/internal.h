@@ -23,6 +23,23 @@ struct Variant {
                          const float2* tw, int64_t batch, hipStream_t stream);
 };
 
+// A two-pass schedule for large lengths: pass 1 runs stages 1..a on blocks of
+// 2^a positions into a workspace, pass 2 runs stages a+1..m on columns.
+struct TwoPass {
+    int m;
+    int a;
+    int c1, c2;              // groups per workgroup in each pass
+    int threads1, threads2;  // workgroup sizes
+    int lds1, lds2;          // LDS bytes
+    hipError_t (*pass1)(const float* xr, const float* xi, float* wr, float* wi, const float2* tw, int64_t batch,
+                        hipStream_t stream);
+    hipError_t (*pass2)(const float* wr, const float* wi, float* yr, float* yi, const float2* tw, int64_t batch,
+                        hipStream_t stream);
+};
+
+// Compiled two-pass schedules for length 2^m (count returned through *count).
+const TwoPass* two_pass_for(int m, int* count);
+
 // All compiled variants for length 2^m (count returned through *count).
 const Variant* variants_for(int m, int* count);
 

@@ -81,7 +81,7 @@ def all_variants(m):
     return out
 
 
-@pytest.mark.parametrize("m", range(0, 16))
+@pytest.mark.parametrize("m", range(0, 17))
 def test_every_length_and_schedule(m):
     n = 1 << m
     # a batch that is not a multiple of any workgroup's transform count, and
@@ -96,7 +96,7 @@ def test_every_length_and_schedule(m):
         assert_within_tol(yr, yi, rr, ri, n)
 
 
-@pytest.mark.parametrize("m", [0, 1, 4, 7, 10, 12, 15])
+@pytest.mark.parametrize("m", [0, 1, 4, 7, 10, 12, 15, 16])
 def test_adjoint_every_length(m):
     n = 1 << m
     batch = max(1, min(257, (1 << 18) // n))
@@ -110,7 +110,7 @@ def test_adjoint_every_length(m):
         assert_within_tol(yr, yi, rr, ri, n)
 
 
-@pytest.mark.parametrize("m", [4, 10, 15])
+@pytest.mark.parametrize("m", [4, 10, 15, 16])
 def test_closed_forms_exact(m):
     n = 1 << m
     batch = 3
@@ -126,7 +126,7 @@ def test_closed_forms_exact(m):
     assert np.array_equal(yr, expect) and np.all(yi == 0.0)
 
 
-@pytest.mark.parametrize("m", [3, 10, 13])
+@pytest.mark.parametrize("m", [3, 10, 13, 16])
 def test_single_tone_sign(m):
     n = 1 << m
     k0 = n // 3
@@ -223,3 +223,45 @@ def test_batch_one_and_large_batch_small_n():
         yr, yi = gpu_exec(n, batch, xr, xi)
         mr, mi = oracle.split_fft_f32(xr.numpy(), xi.numpy())
         assert_bit_exact(yr, yi, mr, mi)
+
+
+def test_two_pass_chunks_and_caller_workspace():
+    # more rows than one workspace chunk, in place, then with a caller workspace
+    n, batch = 1 << 16, 131
+    xr, xi = inputs.draw_planes(n, batch, "normal", 13)
+    mr, mi = oracle.split_fft_f32(xr.numpy(), xi.numpy())
+    say("  two-pass n=%d batch=%d" % (n, batch))
+    with Plan(n, batch) as p:
+        ws = p.workspace_bytes()
+        assert 0 < ws <= (64 << 20)
+        assert ws < 2 * 4 * n * batch  # chunked
+        ar, ai = xr.cuda(), xi.cuda()
+        p.exec(ar, ai, ar, ai)
+        torch.cuda.synchronize()
+        assert_bit_exact(to_np(ar), to_np(ai), mr, mi)
+        L = binding.lib()
+        w = torch.empty(ws // 4, device="cuda")
+        br, bi = xr.cuda(), xi.cuda()
+        yr, yi = torch.empty_like(br), torch.empty_like(bi)
+        s = torch.cuda.current_stream().cuda_stream
+        assert L.split_dft_exec_ws(p.handle, br.data_ptr(), bi.data_ptr(), yr.data_ptr(), yi.data_ptr(),
+                                   w.data_ptr(), ws, s) == 0
+        torch.cuda.synchronize()
+        assert_bit_exact(to_np(yr), to_np(yi), mr, mi)
+        hr, hi = oracle.split_adjoint_f32(xr.numpy(), xi.numpy())
+        assert L.split_dft_adjoint_ws(p.handle, br.data_ptr(), bi.data_ptr(), yr.data_ptr(), yi.data_ptr(),
+                                      w.data_ptr(), ws, s) == 0
+        torch.cuda.synchronize()
+        assert_bit_exact(to_np(yr), to_np(yi), hr, hi)
+        # too small, misaligned or overlapping workspaces are rejected before any launch
+        assert L.split_dft_exec_ws(p.handle, br.data_ptr(), bi.data_ptr(), yr.data_ptr(), yi.data_ptr(),
+                                   w.data_ptr(), ws - 16, s) == 2
+        assert L.split_dft_exec_ws(p.handle, br.data_ptr(), bi.data_ptr(), yr.data_ptr(), yi.data_ptr(),
+                                   w.data_ptr() + 4, ws, s) == 4
+        assert L.split_dft_exec_ws(p.handle, br.data_ptr(), bi.data_ptr(), yr.data_ptr(), yi.data_ptr(),
+                                   yr.data_ptr(), ws, s) == 5
+
+
+def test_single_pass_plans_need_no_workspace():
+    with Plan(1024, 8) as p:
+        assert p.workspace_bytes() == 0
