@@ -128,7 +128,7 @@ split_dft_status split_dft_destroy(split_dft_plan_t plan);
 
 /* Workspace bytes a plan needs beyond inputs and outputs: 0 for lengths
  * handled in a single pass; for two-pass plans (n = 2^16 by default) the
- * intermediate of one chunk of transforms, both planes (at most 64 MiB or one
+ * intermediate of one chunk of transforms, both planes (at most 128 MiB or one
  * transform).  0 for a NULL or destroyed plan. */
 size_t split_dft_workspace_bytes(split_dft_plan_t plan);
 

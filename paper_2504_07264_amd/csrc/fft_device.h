@@ -139,8 +139,10 @@ __device__ __forceinline__ void lds_get(float (&v)[E], const float* lds, int t)
 }
 
 // Passes P, P+1, ... of a group of 2^M positions: exchange through LDS, then
-// the pass's stages (A, lo_g as for stages()).
-template <int M, int RB, int P, bool SPLIT, int E, int TWOFF, int A = 0>
+// the pass's stages (A, lo_g as for stages()).  SYNC_T is the thread count
+// whose exchange ordering is needed (the group's own T when its threads are
+// consecutive lanes; anything above 64 forces workgroup barriers).
+template <int M, int RB, int P, bool SPLIT, int E, int TWOFF, int A = 0, int SYNC_T = (1 << (M - RB))>
 __device__ __forceinline__ void later_passes(float (&vr)[E], float (&vi)[E], float* lr, float* li, int t,
                                              const float2* __restrict__ tw, int lo_g = 0)
 {
@@ -150,23 +152,23 @@ __device__ __forceinline__ void later_passes(float (&vr)[E], float (&vi)[E], flo
         using Cur = Pass<M, RB, P>;
         if constexpr (SPLIT) {  // one plane at a time through the same LDS
             lds_put<E, LT, Prev::S, Prev::RP, Cur::S, Cur::RP>(vr, lr, t);
-            xsync<(1 << (M - RB))>();
+            xsync<SYNC_T>();
             lds_get<E, LT, Cur::S, Cur::RP>(vr, lr, t);
-            xsync<(1 << (M - RB))>();
+            xsync<SYNC_T>();
             lds_put<E, LT, Prev::S, Prev::RP, Cur::S, Cur::RP>(vi, lr, t);
-            xsync<(1 << (M - RB))>();
+            xsync<SYNC_T>();
             lds_get<E, LT, Cur::S, Cur::RP>(vi, lr, t);
-            xsync<(1 << (M - RB))>();
+            xsync<SYNC_T>();
         } else {
             lds_put<E, LT, Prev::S, Prev::RP, Cur::S, Cur::RP>(vr, lr, t);
             lds_put<E, LT, Prev::S, Prev::RP, Cur::S, Cur::RP>(vi, li, t);
-            xsync<(1 << (M - RB))>();
+            xsync<SYNC_T>();
             lds_get<E, LT, Cur::S, Cur::RP>(vr, lr, t);
             lds_get<E, LT, Cur::S, Cur::RP>(vi, li, t);
-            xsync<(1 << (M - RB))>();
+            xsync<SYNC_T>();
         }
         stages<E, LT, Cur::S, Cur::RP, TWOFF, A>(vr, vi, t, tw, lo_g);
-        later_passes<M, RB, P + 1, SPLIT, E, TWOFF, A>(vr, vi, lr, li, t, tw, lo_g);
+        later_passes<M, RB, P + 1, SPLIT, E, TWOFF, A, SYNC_T>(vr, vi, lr, li, t, tw, lo_g);
     }
 }
 

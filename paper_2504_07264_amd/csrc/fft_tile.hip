@@ -28,10 +28,14 @@
 namespace splitdft {
 namespace {
 
-template <int M_, int A_, int PASS_, int RB_, int C_, bool SPLIT_>
+// GF: lanes run over the tile's groups first (thread t of group g is
+// tid = g + C * t), so that the per-group twiddles of pass 2 (index
+// lo + (ql << A), lo = the group's column) are contiguous across a wave; the
+// groups then span waves and exchanges use workgroup barriers.
+template <int M_, int A_, int PASS_, int RB_, int C_, bool SPLIT_, bool GF_ = false>
 struct TileCfg {
     static constexpr int M = M_, A = A_, PASS = PASS_, RB = RB_, C = C_;
-    static constexpr bool SPLIT = SPLIT_;
+    static constexpr bool SPLIT = SPLIT_, GF = GF_;
     static constexpr int N = 1 << M;
     static constexpr int MA = PASS == 1 ? A : M - A;  // log2 positions per group
     static constexpr int R = 1 << MA;
@@ -136,8 +140,8 @@ split_fft_tile_kernel(const float* xr, const float* xi, float* yr, float* yi, co
     constexpr int E = TC::E, LT = TC::LT, T = TC::T, C = TC::C;
     __shared__ float lds[TC::LDS_WORDS];
     const int tid = threadIdx.x;
-    const int g = tid >> LT;  // group (column) within the tile
-    const int t = tid & (T - 1);
+    const int g = TC::GF ? tid % C : tid >> LT;  // group (column) within the tile
+    const int t = TC::GF ? tid / C : tid & (T - 1);
     const int64_t b = blockIdx.x / tiles_per_transform;
     const int col0 = (blockIdx.x % tiles_per_transform) * C;
     const int64_t base = b * TC::N;
@@ -166,7 +170,8 @@ split_fft_tile_kernel(const float* xr, const float* xi, float* yr, float* yi, co
     const int lo_g = TC::PASS == 1 ? 0 : col0 + g;
     stages<E, LT, 0, Pass<TC::MA, TC::RB, 0>::RP, 0, TC::TW_SHIFT>(vr, vi, t, tw, lo_g);
     if constexpr (TC::NP > 1)
-        later_passes<TC::MA, TC::RB, 1, TC::SPLIT, E, 0, TC::TW_SHIFT>(vr, vi, lr, li, t, tw, lo_g);
+        later_passes<TC::MA, TC::RB, 1, TC::SPLIT, E, 0, TC::TW_SHIFT, TC::GF ? 1024 : T>(vr, vi, lr, li, t, tw,
+                                                                                       lo_g);
 
     // the group's slot is free again (its last exchange ended with a sync)
     if constexpr (TC::SPLIT) {
@@ -209,30 +214,34 @@ hipError_t launch_tile(const float* xr, const float* xi, float* yr, float* yi, c
     return hipGetLastError();
 }
 
-template <int M, int A, int RB1, int C1, bool SPLIT1, int RB2, int C2, bool SPLIT2>
+template <int M, int A, int RB1, int C1, bool SPLIT1, int RB2, int C2, bool SPLIT2, bool GF2 = false>
 constexpr TwoPass make_two_pass()
 {
     using P1 = TileCfg<M, A, 1, RB1, C1, SPLIT1>;
-    using P2 = TileCfg<M, A, 2, RB2, C2, SPLIT2>;
-    return TwoPass{M,          A,          C1,         C2,         P1::THREADS, P2::THREADS,
-                   4 * P1::LDS_WORDS, 4 * P2::LDS_WORDS, &launch_tile<P1>, &launch_tile<P2>};
+    using P2 = TileCfg<M, A, 2, RB2, C2, SPLIT2, GF2>;
+    return TwoPass{M,  A,  C1, C2, P1::THREADS, P2::THREADS, 4 * P1::LDS_WORDS, 4 * P2::LDS_WORDS, GF2,
+                   &launch_tile<P1>, &launch_tile<P2>};
 }
 
-//                                   M   A  RB1 C1 SPLIT1 RB2 C2 SPLIT2
-const TwoPass kTwoPass14[] = {make_two_pass<14, 8, 4, 32, true, 4, 32, true>()};
-const TwoPass kTwoPass15[] = {make_two_pass<15, 8, 4, 32, true, 4, 32, true>(),
+//                                   M   A  RB1 C1 SPLIT1 RB2 C2 SPLIT2 GF2
+const TwoPass kTwoPass14[] = {make_two_pass<14, 8, 4, 32, true, 4, 32, true, true>(),
+                              make_two_pass<14, 8, 4, 32, true, 4, 32, true>()};
+const TwoPass kTwoPass15[] = {make_two_pass<15, 8, 4, 32, true, 4, 32, true, true>(),
+                              make_two_pass<15, 8, 4, 32, true, 4, 32, true>(),
                               make_two_pass<15, 8, 4, 16, false, 4, 32, false>()};
-const TwoPass kTwoPass16[] = {make_two_pass<16, 8, 4, 32, true, 4, 32, true>(),
-                              make_two_pass<16, 8, 4, 16, false, 4, 16, false>()};
+const TwoPass kTwoPass16[] = {make_two_pass<16, 8, 4, 32, true, 4, 32, true, true>(),
+                              make_two_pass<16, 8, 4, 32, true, 4, 32, true>(),
+                              make_two_pass<16, 8, 4, 16, false, 4, 16, false>(),
+                              make_two_pass<16, 8, 4, 32, true, 4, 64, true, true>()};
 
 }  // namespace
 
 const TwoPass* two_pass_for(int m, int* count)
 {
     switch (m) {
-    case 14: *count = 1; return kTwoPass14;
-    case 15: *count = 2; return kTwoPass15;
-    case 16: *count = 2; return kTwoPass16;
+    case 14: *count = 2; return kTwoPass14;
+    case 15: *count = 3; return kTwoPass15;
+    case 16: *count = 4; return kTwoPass16;
     default: *count = 0; return nullptr;
     }
 }

@@ -31,6 +31,7 @@ struct TwoPass {
     int c1, c2;              // groups per workgroup in each pass
     int threads1, threads2;  // workgroup sizes
     int lds1, lds2;          // LDS bytes
+    bool gf2;                // pass 2 lanes run over columns first
     hipError_t (*pass1)(const float* xr, const float* xi, float* wr, float* wi, const float2* tw, int64_t batch,
                         hipStream_t stream);
     hipError_t (*pass2)(const float* wr, const float* wi, float* yr, float* yi, const float2* tw, int64_t batch,
