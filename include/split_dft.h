@@ -149,6 +149,57 @@ split_dft_status split_dft_plan_describe(split_dft_plan_t plan, char *buf, size_
  * HIP call. */
 split_dft_status split_dft_twiddle_table(int m, float *c, float *s);
 
+/* ---- grouped execution: a ragged batch of mixed lengths --------------------
+ *
+ * `count` transforms of lengths lengths[k] = 2^m_k, 2 <= m_k <= 16, laid out
+ * back to back in each plane: transform k occupies [offset_k, offset_k + N_k)
+ * with offset_0 = 0 and offset_(k+1) = offset_k + N_k (split_dft_many_offsets).
+ * Each transform is the operation of split_dft_exec (eq. (6) applied in order,
+ * bit-identical to it), and the adjoint that of split_dft_adjoint.  One call
+ * is one persistent kernel launch: workgroups take work items (a group of
+ * short transforms of one length, or one transform of length >= 2^14 run
+ * through a per-workgroup workspace) from a device counter, largest first.
+ * The counter returns to zero at the end of every launch, so launches can be
+ * replayed from a graph; launches of one grouped plan must not overlap in
+ * time (use one stream).  Pointer rules as for split_dft_exec (16-byte
+ * aligned, outputs may coincide exactly with their own direction's inputs).
+ */
+typedef struct split_dft_many_s *split_dft_many_t;
+typedef struct split_dft_graph_s *split_dft_graph_t;
+
+/* flags: bits 0-7 precision (SPLIT_DFT_FP32 only); bits 8-15 kernel build
+ * (0 = default, k = build k-1: 0 two workgroups per CU, 1 one); bits 16-23
+ * workgroups per CU (0 = as many as fit).  Allocates the device-side item
+ * list, offsets, twiddle table and, when some length is >= 2^14, a workspace
+ * of 512 KiB per persistent workgroup. */
+split_dft_status split_dft_many_plan(split_dft_many_t *out, const int64_t *lengths, int64_t count,
+                                     uint32_t flags);
+/* offsets: count + 1 entries (the last is the total number of points). */
+split_dft_status split_dft_many_offsets(split_dft_many_t plan, int64_t *offsets);
+/* Any pointer may be NULL. */
+split_dft_status split_dft_many_info(split_dft_many_t plan, int64_t *count, int64_t *points,
+                                     int *workgroups, int *items, size_t *workspace_bytes);
+/* Forward transforms of every (xr, xi) row into (yr, yi). */
+split_dft_status split_dft_many_exec(split_dft_many_t plan, const float *xr, const float *xi,
+                                     float *yr, float *yi, void *stream);
+/* Adjoint transforms of every (gr, gi) row into (gxr, gxi). */
+split_dft_status split_dft_many_adjoint(split_dft_many_t plan, const float *gr, const float *gi,
+                                        float *gxr, float *gxi, void *stream);
+/* Both in one launch (forward of x, adjoint of g); the forward and adjoint
+ * arrays must not overlap each other. */
+split_dft_status split_dft_many_exec_adjoint(split_dft_many_t plan, const float *xr, const float *xi,
+                                             float *yr, float *yi, const float *gr, const float *gi,
+                                             float *gxr, float *gxi, void *stream);
+/* Capture split_dft_many_exec_adjoint (or split_dft_many_exec when gr, gi,
+ * gxr, gxi are all NULL) on these fixed buffers into an instantiated HIP
+ * graph, using a private capturing stream. */
+split_dft_status split_dft_many_graph(split_dft_many_t plan, const float *xr, const float *xi,
+                                      float *yr, float *yi, const float *gr, const float *gi,
+                                      float *gxr, float *gxi, split_dft_graph_t *out);
+split_dft_status split_dft_graph_launch(split_dft_graph_t graph, void *stream);
+split_dft_status split_dft_graph_destroy(split_dft_graph_t graph);
+split_dft_status split_dft_many_destroy(split_dft_many_t plan);
+
 const char *split_dft_status_string(split_dft_status status);
 const char *split_dft_last_error(void);
 

@@ -7,9 +7,9 @@ HIP kernels behind the C ABI of include/split_dft.h.
 
 The library is loaded on first use; a missing build raises.
 """
-from .binding import (FP32, Plan, SplitDFTError, cached_plan, split_dft,  # noqa: F401
-                      split_dft_adjoint, twiddle_table, variant_flag)
+from .binding import (FP32, ManyGraph, ManyPlan, Plan, SplitDFTError, cached_plan,  # noqa: F401
+                      many_flags, split_dft, split_dft_adjoint, twiddle_table, variant_flag)
 from .autograd import SplitDFTFunction, split_dft_autograd  # noqa: F401
 
-__all__ = ["Plan", "SplitDFTError", "split_dft", "split_dft_adjoint", "split_dft_autograd",
+__all__ = ["Plan", "ManyPlan", "ManyGraph", "many_flags", "SplitDFTError", "split_dft", "split_dft_adjoint", "split_dft_autograd",
            "SplitDFTFunction", "twiddle_table", "variant_flag", "cached_plan", "FP32"]

@@ -38,6 +38,9 @@ EXPORTED = (
     "split_dft_destroy",
     "split_dft_workspace_bytes", "split_dft_plan_info", "split_dft_plan_describe", "split_dft_twiddle_table",
     "split_dft_status_string", "split_dft_last_error",
+    "split_dft_many_plan", "split_dft_many_offsets", "split_dft_many_info", "split_dft_many_exec",
+    "split_dft_many_adjoint", "split_dft_many_exec_adjoint", "split_dft_many_graph", "split_dft_graph_launch",
+    "split_dft_graph_destroy", "split_dft_many_destroy",
 )
 
 _lib = None
@@ -84,6 +87,26 @@ def lib() -> ctypes.CDLL:
         L.split_dft_plan_describe.restype = ci
         L.split_dft_twiddle_table.argtypes = [ci, vp, vp]
         L.split_dft_twiddle_table.restype = ci
+        L.split_dft_many_plan.argtypes = [ctypes.POINTER(vp), vp, i64, u32]
+        L.split_dft_many_plan.restype = ci
+        L.split_dft_many_offsets.argtypes = [vp, vp]
+        L.split_dft_many_offsets.restype = ci
+        L.split_dft_many_info.argtypes = [vp, pi64, pi64, pi, pi, ctypes.POINTER(ctypes.c_size_t)]
+        L.split_dft_many_info.restype = ci
+        for name in ("split_dft_many_exec", "split_dft_many_adjoint"):
+            fn = getattr(L, name)
+            fn.argtypes = [vp, vp, vp, vp, vp, vp]
+            fn.restype = ci
+        L.split_dft_many_exec_adjoint.argtypes = [vp] + [vp] * 8 + [vp]
+        L.split_dft_many_exec_adjoint.restype = ci
+        L.split_dft_many_graph.argtypes = [vp] + [vp] * 8 + [ctypes.POINTER(vp)]
+        L.split_dft_many_graph.restype = ci
+        L.split_dft_graph_launch.argtypes = [vp, vp]
+        L.split_dft_graph_launch.restype = ci
+        L.split_dft_graph_destroy.argtypes = [vp]
+        L.split_dft_graph_destroy.restype = ci
+        L.split_dft_many_destroy.argtypes = [vp]
+        L.split_dft_many_destroy.restype = ci
         L.split_dft_status_string.argtypes = [ci]
         L.split_dft_status_string.restype = ctypes.c_char_p
         L.split_dft_last_error.argtypes = []
@@ -234,3 +257,124 @@ def split_dft_adjoint(gr: torch.Tensor, gi: torch.Tensor, out=None):
     p = cached_plan(n, gr.numel() // max(n, 1), gr.device)
     r, i = (None, None) if out is None else out
     return p.adjoint(gr, gi, r, i)
+
+
+def many_flags(build: int = -1, workgroups_per_cu: int = 0) -> int:
+    """Grouped-plan flag bits: kernel build (-1 = default) and workgroups per CU (0 = max)."""
+    return ((int(build) + 1) << 8) + (int(workgroups_per_cu) << 16)
+
+
+class ManyPlan:
+    """Grouped plan for a ragged batch: transform k has length lengths[k] and
+    occupies [offsets[k], offsets[k+1]) of each flat FP32 plane."""
+
+    def __init__(self, lengths, flags: int = FP32, device=None):
+        import numpy as np
+
+        L = lib()
+        self.lengths = np.ascontiguousarray(np.asarray(lengths, dtype=np.int64).ravel())
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
+            else torch.device(device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(L.split_dft_many_plan(ctypes.byref(h), self.lengths.ctypes.data, self.lengths.size, int(flags)))
+        self._h = h
+        offs = np.empty(self.lengths.size + 1, np.int64)
+        check(L.split_dft_many_offsets(h, offs.ctypes.data))
+        self.offsets = offs
+        self.points = int(offs[-1])
+
+    def info(self):
+        c, p = ctypes.c_int64(), ctypes.c_int64()
+        wg, it = ctypes.c_int(), ctypes.c_int()
+        ws = ctypes.c_size_t()
+        check(lib().split_dft_many_info(self._h, ctypes.byref(c), ctypes.byref(p), ctypes.byref(wg),
+                                        ctypes.byref(it), ctypes.byref(ws)))
+        return {"count": c.value, "points": p.value, "workgroups": wg.value, "items": it.value,
+                "workspace_bytes": ws.value}
+
+    def _plane(self, t, name):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float32:
+            raise TypeError("%s must be a float32 tensor" % name)
+        if t.device != self.device or not t.is_contiguous() or t.numel() != self.points:
+            raise ValueError("%s must be a contiguous tensor of %d floats on %s" % (name, self.points, self.device))
+        return t.data_ptr()
+
+    def _new(self, like):
+        return torch.empty_like(like)
+
+    def exec(self, xr, xi, yr=None, yi=None):
+        yr = self._new(xr) if yr is None else yr
+        yi = self._new(xi) if yi is None else yi
+        args = [self._plane(t, n) for t, n in ((xr, "xr"), (xi, "xi"), (yr, "yr"), (yi, "yi"))]
+        with torch.cuda.device(self.device):
+            check(lib().split_dft_many_exec(self._h, *args, _stream_handle(self.device)))
+        return yr, yi
+
+    def adjoint(self, gr, gi, gxr=None, gxi=None):
+        gxr = self._new(gr) if gxr is None else gxr
+        gxi = self._new(gi) if gxi is None else gxi
+        args = [self._plane(t, n) for t, n in ((gr, "gr"), (gi, "gi"), (gxr, "gxr"), (gxi, "gxi"))]
+        with torch.cuda.device(self.device):
+            check(lib().split_dft_many_adjoint(self._h, *args, _stream_handle(self.device)))
+        return gxr, gxi
+
+    def exec_adjoint(self, xr, xi, gr, gi, out=None):
+        yr, yi, gxr, gxi = out if out is not None else (self._new(xr), self._new(xi), self._new(gr), self._new(gi))
+        names = ("xr", "xi", "yr", "yi", "gr", "gi", "gxr", "gxi")
+        args = [self._plane(t, n) for t, n in zip((xr, xi, yr, yi, gr, gi, gxr, gxi), names)]
+        with torch.cuda.device(self.device):
+            check(lib().split_dft_many_exec_adjoint(self._h, *args, _stream_handle(self.device)))
+        return yr, yi, gxr, gxi
+
+    def graph(self, xr, xi, yr, yi, gr=None, gi=None, gxr=None, gxi=None):
+        """Capture exec (and the adjoint when g planes are given) on these buffers."""
+        ptrs = [self._plane(t, n) for t, n in ((xr, "xr"), (xi, "xi"), (yr, "yr"), (yi, "yi"))]
+        if gr is None:
+            ptrs += [None] * 4
+        else:
+            ptrs += [self._plane(t, n) for t, n in ((gr, "gr"), (gi, "gi"), (gxr, "gxr"), (gxi, "gxi"))]
+        g = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib().split_dft_many_graph(self._h, *ptrs, ctypes.byref(g)))
+        return ManyGraph(g, self)
+
+    def close(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h is not None and h.value and _lib is not None:
+            check(_lib.split_dft_many_destroy(h))
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class ManyGraph:
+    """An instantiated HIP graph of one grouped launch on fixed buffers."""
+
+    def __init__(self, handle, plan):
+        self._h = handle
+        self._plan = plan  # keeps the plan's device data alive
+
+    def launch(self, stream=None):
+        s = _stream_handle(self._plan.device) if stream is None else stream
+        check(lib().split_dft_graph_launch(self._h, s))
+
+    def close(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h is not None and h.value and _lib is not None:
+            check(_lib.split_dft_graph_destroy(h))
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -53,6 +53,12 @@ split_dft_status fail(split_dft_status st, const std::string& msg)
     return st;
 }
 
+}  // namespace
+
+void splitdft::set_last_error(const std::string& msg) { g_last_error = msg; }
+
+namespace {
+
 split_dft_status fail_hip(hipError_t e, const char* what)
 {
     g_last_error = std::string(what) + ": " + hipGetErrorString(e);

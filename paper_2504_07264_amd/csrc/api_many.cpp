@@ -1,0 +1,462 @@
+// C ABI of grouped execution: a ragged batch of transforms of different
+// power-of-two lengths, forward and/or adjoint, in one persistent launch,
+// optionally captured once into a HIP graph.
+#include "../../include/split_dft.h"
+#include "internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+struct split_dft_many_s {
+    int64_t count;
+    int64_t points;
+    int device;
+    int variant;  // grouped-kernel build
+    int grid;     // persistent workgroups
+    std::vector<int64_t> offsets;  // host copy, count + 1 entries
+    int64_t* d_offsets;
+    int32_t* d_order;
+    splitdft::ManyItem* d_items_one;   // forward only (direction 0)
+    int n_one;
+    splitdft::ManyItem* d_items_both;  // forward (0) and adjoint (1) interleaved
+    int n_both;
+    int* d_queue;
+    float* d_ws;
+    size_t ws_bytes;
+    float2* d_tw;
+};
+
+struct split_dft_graph_s {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+namespace {
+
+std::mutex g_mu;
+std::unordered_set<const void*>& live()
+{
+    static auto* s = new std::unordered_set<const void*>();
+    return *s;
+}
+
+bool is_live(const void* p)
+{
+    std::lock_guard<std::mutex> g(g_mu);
+    return live().count(p) != 0;
+}
+
+void set_live(const void* p, bool on)
+{
+    std::lock_guard<std::mutex> g(g_mu);
+    if (on)
+        live().insert(p);
+    else
+        live().erase(p);
+}
+
+bool ranges_overlap(const void* a, size_t abytes, const void* b, size_t bbytes)
+{
+    const auto x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + bbytes && y < x + abytes;
+}
+
+void free_many(split_dft_many_s* p)
+{
+    for (void* q : {static_cast<void*>(p->d_offsets), static_cast<void*>(p->d_order),
+                    static_cast<void*>(p->d_items_one), static_cast<void*>(p->d_items_both),
+                    static_cast<void*>(p->d_queue), static_cast<void*>(p->d_ws), static_cast<void*>(p->d_tw)})
+        if (q)
+            (void)hipFree(q);
+    delete p;
+}
+
+template <class T>
+hipError_t upload(T** dst, const std::vector<T>& src)
+{
+    *dst = nullptr;
+    if (src.empty())
+        return hipSuccess;
+    hipError_t e = hipMalloc(dst, sizeof(T) * src.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+    return e;
+}
+
+// Planes of one direction: inputs and outputs, checked for NULL, alignment
+// and partial overlap (an output may coincide exactly with an input of its
+// own direction: every item reads its transforms before writing them).
+split_dft_status check_dir(const split_dft_many_s* p, const float* ar, const float* ai, const float* br,
+                           const float* bi, std::string* msg)
+{
+    if (!ar || !ai || !br || !bi) {
+        *msg = "a data pointer is NULL";
+        return SPLIT_DFT_ERR_NULL_POINTER;
+    }
+    for (const void* q : {static_cast<const void*>(ar), static_cast<const void*>(ai), static_cast<const void*>(br),
+                          static_cast<const void*>(bi)})
+        if (reinterpret_cast<uintptr_t>(q) % 16 != 0) {
+            *msg = "data pointers must be 16-byte aligned";
+            return SPLIT_DFT_ERR_MISALIGNED;
+        }
+    const size_t bytes = static_cast<size_t>(p->points) * sizeof(float);
+    if (ranges_overlap(br, bytes, bi, bytes)) {
+        *msg = "the two output planes overlap";
+        return SPLIT_DFT_ERR_ALIASING;
+    }
+    for (const float* out : {br, bi})
+        for (const float* in : {ar, ai})
+            if (out != in && ranges_overlap(out, bytes, in, bytes)) {
+                *msg = "an output partially overlaps an input";
+                return SPLIT_DFT_ERR_ALIASING;
+            }
+    return SPLIT_DFT_OK;
+}
+
+split_dft_status many_launch(split_dft_many_t p, const float* xr, const float* xi, float* yr, float* yi,
+                             const float* gr, const float* gi, float* gxr, float* gxi, bool fwd, bool adj,
+                             hipStream_t stream, std::string* msg)
+{
+    if (!p || !is_live(p)) {
+        *msg = "grouped plan is NULL, destroyed or not created by split_dft_many_plan";
+        return SPLIT_DFT_ERR_INVALID_PLAN;
+    }
+    const size_t bytes = static_cast<size_t>(p->points) * sizeof(float);
+    split_dft_status st = SPLIT_DFT_OK;
+    if (fwd && (st = check_dir(p, xr, xi, yr, yi, msg)) != SPLIT_DFT_OK)
+        return st;
+    if (adj && (st = check_dir(p, gr, gi, gxr, gxi, msg)) != SPLIT_DFT_OK)
+        return st;
+    if (fwd && adj) {
+        // the two directions run concurrently: no output of one may touch the other's arrays
+        for (const float* out : {yr, yi})
+            for (const float* other : {gr, gi, static_cast<const float*>(gxr), static_cast<const float*>(gxi)})
+                if (ranges_overlap(out, bytes, other, bytes)) {
+                    *msg = "forward and adjoint arrays overlap";
+                    return SPLIT_DFT_ERR_ALIASING;
+                }
+        for (const float* out : {gxr, gxi})
+            for (const float* other : {xr, xi})
+                if (ranges_overlap(out, bytes, other, bytes)) {
+                    *msg = "forward and adjoint arrays overlap";
+                    return SPLIT_DFT_ERR_ALIASING;
+                }
+    }
+    splitdft::ManyArgs a{};
+    int d = 0;
+    if (fwd) {
+        a.in_r[d] = xr, a.in_i[d] = xi, a.out_r[d] = yr, a.out_i[d] = yi;
+        ++d;
+    }
+    if (adj) {
+        // C g_r - S g_i and S g_r + C g_i: the forward scheme on (g_i, g_r), outputs exchanged
+        a.in_r[d] = gi, a.in_i[d] = gr, a.out_r[d] = gxi, a.out_i[d] = gxr;
+        ++d;
+    }
+    a.offsets = p->d_offsets;
+    a.order = p->d_order;
+    a.items = d == 2 ? p->d_items_both : p->d_items_one;
+    a.nitems = d == 2 ? p->n_both : p->n_one;
+    a.queue = p->d_queue;
+    a.ws = p->d_ws;
+    a.tw = p->d_tw;
+    const hipError_t e = splitdft::launch_many(p->variant, a, p->grid, stream);
+    if (e != hipSuccess) {
+        *msg = std::string("grouped kernel launch: ") + hipGetErrorString(e);
+        return SPLIT_DFT_ERR_HIP;
+    }
+    return SPLIT_DFT_OK;
+}
+
+split_dft_status fail(split_dft_status st, const std::string& msg)
+{
+    splitdft::set_last_error(msg);
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+split_dft_status split_dft_many_plan(split_dft_many_t* out, const int64_t* lengths, int64_t count, uint32_t flags)
+{
+    using namespace splitdft;
+    if (!out || !lengths)
+        return fail(SPLIT_DFT_ERR_NULL_POINTER, "out or lengths is NULL");
+    if (count < 1 || count > INT32_MAX)
+        return fail(SPLIT_DFT_ERR_INVALID_BATCH, "count must be in [1, 2^31 - 1]");
+    if ((flags & 0xffu) != SPLIT_DFT_FP32 || (flags >> 24) != 0)
+        return fail(SPLIT_DFT_ERR_UNSUPPORTED, "unsupported flags " + std::to_string(flags));
+    const int variant_sel = static_cast<int>((flags >> 8) & 0xffu);  // 0 = default build, k = build k-1
+    const int wg_per_cu = static_cast<int>((flags >> 16) & 0xffu);   // 0 = as many as fit
+    if (variant_sel > kManyKernelVariants)
+        return fail(SPLIT_DFT_ERR_UNSUPPORTED, "unknown grouped kernel build");
+
+    std::vector<int64_t> offs(static_cast<size_t>(count) + 1, 0);
+    std::vector<int> logs(static_cast<size_t>(count));
+    bool any_large = false;
+    for (int64_t k = 0; k < count; ++k) {
+        const int64_t n = lengths[k];
+        int m = 0;
+        while (m < 62 && (int64_t{1} << m) < n)
+            ++m;
+        if (n < 1 || (int64_t{1} << m) != n || m < kManyMinLog2N || m > kManyMaxLog2N)
+            return fail(SPLIT_DFT_ERR_INVALID_LENGTH,
+                        "length " + std::to_string(k) + " = " + std::to_string(n) + " is not 2^m, 2 <= m <= 16");
+        logs[static_cast<size_t>(k)] = m;
+        any_large = any_large || m > 13;
+        if (offs[static_cast<size_t>(k)] > INT64_MAX / 8 - n)
+            return fail(SPLIT_DFT_ERR_INVALID_BATCH, "total length overflows");
+        offs[static_cast<size_t>(k) + 1] = offs[static_cast<size_t>(k)] + n;
+    }
+
+    // transforms grouped by length, longest first; items listed longest first
+    std::vector<int32_t> order(static_cast<size_t>(count));
+    for (int64_t k = 0; k < count; ++k)
+        order[static_cast<size_t>(k)] = static_cast<int32_t>(k);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return logs[static_cast<size_t>(a)] > logs[static_cast<size_t>(b)]; });
+    std::vector<ManyItem> one, both;
+    for (size_t i = 0; i < order.size();) {
+        const int m = logs[static_cast<size_t>(order[i])];
+        size_t j = i;
+        while (j < order.size() && logs[static_cast<size_t>(order[j])] == m)
+            ++j;
+        const size_t per = static_cast<size_t>(many_items_per_group(m));
+        for (size_t s = i; s < j; s += per) {
+            const int cnt = static_cast<int>(std::min(per, j - s));
+            const ManyItem it{m, 0, cnt, 0, static_cast<int64_t>(s)};
+            one.push_back(it);
+            both.push_back(it);
+            ManyItem it2 = it;
+            it2.dir = 1;
+            both.push_back(it2);
+        }
+        i = j;
+    }
+
+    const char* inj = std::getenv("SPLIT_DFT_FAIL_ALLOC");
+    if (inj && *inj && std::strcmp(inj, "0") != 0)
+        return fail(SPLIT_DFT_ERR_OUT_OF_MEMORY, "allocation failure forced by SPLIT_DFT_FAIL_ALLOC");
+
+    auto* p = new (std::nothrow) split_dft_many_s{};
+    if (!p)
+        return fail(SPLIT_DFT_ERR_OUT_OF_MEMORY, "host allocation of the plan failed");
+    p->count = count;
+    p->points = offs.back();
+    p->offsets = offs;
+    p->variant = variant_sel == 0 ? 0 : variant_sel - 1;
+    hipError_t e = hipGetDevice(&p->device);
+    int cus = 0, per_cu = 0;
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+    if (e == hipSuccess)
+        e = many_max_active_per_cu(p->variant, &per_cu);
+    if (e != hipSuccess) {
+        free_many(p);
+        return fail(SPLIT_DFT_ERR_HIP, std::string("device query: ") + hipGetErrorString(e));
+    }
+    if (wg_per_cu > 0 && wg_per_cu < per_cu)
+        per_cu = wg_per_cu;
+    per_cu = per_cu < 1 ? 1 : per_cu;
+    const int64_t items = static_cast<int64_t>(both.size());
+    p->grid = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(cus) * per_cu, std::max<int64_t>(items, 1)));
+
+    std::vector<float> c(static_cast<size_t>(kManyMaxN)), s(static_cast<size_t>(kManyMaxN));
+    build_twiddles_f32(kManyMaxLog2N, c.data(), s.data());
+    std::vector<float2> tw(static_cast<size_t>(kManyMaxN));
+    for (size_t j = 0; j < tw.size(); ++j)
+        tw[j] = make_float2(c[j], s[j]);
+    std::vector<int> queue_init(2, 0);
+    std::vector<int64_t> offs_dev(offs.begin(), offs.end() - 1);
+    e = upload(&p->d_offsets, offs_dev);
+    if (e == hipSuccess)
+        e = upload(&p->d_order, order);
+    if (e == hipSuccess)
+        e = upload(&p->d_items_one, one);
+    if (e == hipSuccess)
+        e = upload(&p->d_items_both, both);
+    if (e == hipSuccess)
+        e = upload(&p->d_queue, queue_init);
+    if (e == hipSuccess)
+        e = upload(&p->d_tw, tw);
+    if (e == hipSuccess && any_large) {
+        p->ws_bytes = static_cast<size_t>(p->grid) * 2 * static_cast<size_t>(kManyMaxN) * sizeof(float);
+        e = hipMalloc(&p->d_ws, p->ws_bytes);
+    }
+    if (e != hipSuccess) {
+        free_many(p);
+        return e == hipErrorOutOfMemory ? fail(SPLIT_DFT_ERR_OUT_OF_MEMORY, "device allocation for the grouped plan")
+                                        : fail(SPLIT_DFT_ERR_HIP, std::string("grouped plan: ") + hipGetErrorString(e));
+    }
+    p->n_one = static_cast<int>(one.size());
+    p->n_both = static_cast<int>(both.size());
+    set_live(p, true);
+    *out = p;
+    return SPLIT_DFT_OK;
+}
+
+split_dft_status split_dft_many_offsets(split_dft_many_t plan, int64_t* offsets)
+{
+    if (!plan || !is_live(plan))
+        return fail(SPLIT_DFT_ERR_INVALID_PLAN, "grouped plan is NULL or destroyed");
+    if (!offsets)
+        return fail(SPLIT_DFT_ERR_NULL_POINTER, "offsets is NULL");
+    std::memcpy(offsets, plan->offsets.data(), sizeof(int64_t) * plan->offsets.size());
+    return SPLIT_DFT_OK;
+}
+
+split_dft_status split_dft_many_info(split_dft_many_t plan, int64_t* count, int64_t* points, int* workgroups,
+                                     int* items, size_t* workspace_bytes)
+{
+    if (!plan || !is_live(plan))
+        return fail(SPLIT_DFT_ERR_INVALID_PLAN, "grouped plan is NULL or destroyed");
+    if (count)
+        *count = plan->count;
+    if (points)
+        *points = plan->points;
+    if (workgroups)
+        *workgroups = plan->grid;
+    if (items)
+        *items = plan->n_both;
+    if (workspace_bytes)
+        *workspace_bytes = plan->ws_bytes;
+    return SPLIT_DFT_OK;
+}
+
+split_dft_status split_dft_many_exec(split_dft_many_t plan, const float* xr, const float* xi, float* yr, float* yi,
+                                     void* stream)
+{
+    std::string msg;
+    const split_dft_status st = many_launch(plan, xr, xi, yr, yi, nullptr, nullptr, nullptr, nullptr, true, false,
+                                            static_cast<hipStream_t>(stream), &msg);
+    return st == SPLIT_DFT_OK ? st : fail(st, msg);
+}
+
+split_dft_status split_dft_many_adjoint(split_dft_many_t plan, const float* gr, const float* gi, float* gxr,
+                                        float* gxi, void* stream)
+{
+    std::string msg;
+    const split_dft_status st = many_launch(plan, nullptr, nullptr, nullptr, nullptr, gr, gi, gxr, gxi, false, true,
+                                            static_cast<hipStream_t>(stream), &msg);
+    return st == SPLIT_DFT_OK ? st : fail(st, msg);
+}
+
+split_dft_status split_dft_many_exec_adjoint(split_dft_many_t plan, const float* xr, const float* xi, float* yr,
+                                             float* yi, const float* gr, const float* gi, float* gxr, float* gxi,
+                                             void* stream)
+{
+    std::string msg;
+    const split_dft_status st =
+        many_launch(plan, xr, xi, yr, yi, gr, gi, gxr, gxi, true, true, static_cast<hipStream_t>(stream), &msg);
+    return st == SPLIT_DFT_OK ? st : fail(st, msg);
+}
+
+split_dft_status split_dft_many_graph(split_dft_many_t plan, const float* xr, const float* xi, float* yr, float* yi,
+                                      const float* gr, const float* gi, float* gxr, float* gxi,
+                                      split_dft_graph_t* out)
+{
+    if (!out)
+        return fail(SPLIT_DFT_ERR_NULL_POINTER, "out is NULL");
+    const bool adj = gr || gi || gxr || gxi;
+    // validate before touching the runtime
+    {
+        std::string msg;
+        if (!plan || !is_live(plan))
+            return fail(SPLIT_DFT_ERR_INVALID_PLAN, "grouped plan is NULL or destroyed");
+        split_dft_status st = check_dir(plan, xr, xi, yr, yi, &msg);
+        if (st == SPLIT_DFT_OK && adj)
+            st = check_dir(plan, gr, gi, gxr, gxi, &msg);
+        if (st != SPLIT_DFT_OK)
+            return fail(st, msg);
+    }
+    hipStream_t s = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess)
+        return fail(SPLIT_DFT_ERR_HIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+    hipGraph_t graph = nullptr;
+    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    std::string msg;
+    split_dft_status st = SPLIT_DFT_OK;
+    if (e == hipSuccess) {
+        st = many_launch(plan, xr, xi, yr, yi, gr, gi, gxr, gxi, true, adj, s, &msg);
+        const hipError_t e2 = hipStreamEndCapture(s, &graph);
+        if (st == SPLIT_DFT_OK && e2 != hipSuccess)
+            e = e2;
+    }
+    (void)hipStreamDestroy(s);
+    if (st != SPLIT_DFT_OK) {
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        return fail(st, msg);
+    }
+    hipGraphExec_t exec = nullptr;
+    if (e == hipSuccess)
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        return fail(SPLIT_DFT_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    auto* g = new (std::nothrow) split_dft_graph_s{graph, exec};
+    if (!g) {
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        return fail(SPLIT_DFT_ERR_OUT_OF_MEMORY, "host allocation of the graph");
+    }
+    set_live(g, true);
+    *out = g;
+    return SPLIT_DFT_OK;
+}
+
+split_dft_status split_dft_graph_launch(split_dft_graph_t graph, void* stream)
+{
+    if (!graph || !is_live(graph))
+        return fail(SPLIT_DFT_ERR_INVALID_PLAN, "graph is NULL or destroyed");
+    const hipError_t e = hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return fail(SPLIT_DFT_ERR_HIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+    return SPLIT_DFT_OK;
+}
+
+split_dft_status split_dft_graph_destroy(split_dft_graph_t graph)
+{
+    if (!graph)
+        return SPLIT_DFT_OK;
+    if (!is_live(graph))
+        return fail(SPLIT_DFT_ERR_INVALID_PLAN, "graph is destroyed");
+    set_live(graph, false);
+    hipError_t e = hipGraphExecDestroy(graph->exec);
+    const hipError_t e2 = hipGraphDestroy(graph->graph);
+    delete graph;
+    if (e == hipSuccess)
+        e = e2;
+    return e == hipSuccess ? SPLIT_DFT_OK : fail(SPLIT_DFT_ERR_HIP, hipGetErrorString(e));
+}
+
+split_dft_status split_dft_many_destroy(split_dft_many_t plan)
+{
+    if (!plan)
+        return SPLIT_DFT_OK;
+    if (!is_live(plan))
+        return fail(SPLIT_DFT_ERR_INVALID_PLAN, "grouped plan is destroyed");
+    set_live(plan, false);
+    int cur = 0;
+    const bool sw = hipGetDevice(&cur) == hipSuccess && cur != plan->device;
+    if (sw)
+        (void)hipSetDevice(plan->device);
+    free_many(plan);
+    if (sw)
+        (void)hipSetDevice(cur);
+    return SPLIT_DFT_OK;
+}
+
+}  // extern "C"

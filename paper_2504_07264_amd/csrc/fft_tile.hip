@@ -21,185 +21,22 @@
 // only wave-level ordering when the group fits in one wave).  The arithmetic
 // is exactly that of eq. (6) in order, so results equal the single-pass
 // kernels' bit for bit.
-#include "fft_device.h"
+#include "fft_tile.h"
 
 #include <climits>
 
 namespace splitdft {
 namespace {
 
-// GF: lanes run over the tile's groups first (thread t of group g is
-// tid = g + C * t), so that the per-group twiddles of pass 2 (index
-// lo + (ql << A), lo = the group's column) are contiguous across a wave; the
-// groups then span waves and exchanges use workgroup barriers.
-template <int M_, int A_, int PASS_, int RB_, int C_, bool SPLIT_, bool GF_ = false>
-struct TileCfg {
-    static constexpr int M = M_, A = A_, PASS = PASS_, RB = RB_, C = C_;
-    static constexpr bool SPLIT = SPLIT_, GF = GF_;
-    static constexpr int N = 1 << M;
-    static constexpr int MA = PASS == 1 ? A : M - A;  // log2 positions per group
-    static constexpr int R = 1 << MA;
-    static constexpr int E = 1 << RB;
-    static constexpr int LT = MA - RB;
-    static constexpr int T = 1 << LT;  // threads per group
-    static constexpr int NP = (MA + RB - 1) / RB;
-    static constexpr int THREADS = C * T;
-    static constexpr int SLOT = lds_index(R) | 1;
-    static constexpr int LDS_WORDS = C * SLOT * (SPLIT ? 1 : 2);
-    static constexpr int TW_SHIFT = PASS == 1 ? 0 : A;
-    static constexpr int GROUPS = PASS == 1 ? (1 << (M - A)) : (1 << A);  // per transform
-    static constexpr int TILES = GROUPS / C;                               // per transform
-    static_assert(C % 4 == 0 && E >= 4 && GROUPS % C == 0, "tile shape");
-};
-
-// Row r of the tile (C contiguous floats) in the source of the pass.
-template <class TC>
-__device__ __forceinline__ int64_t tile_row_offset(int r, int col0)
-{
-    if constexpr (TC::PASS == 1)
-        return static_cast<int64_t>(r) * (TC::N >> TC::A) + col0;  // x row r, blocks col0..
-    else
-        return col0 + (static_cast<int64_t>(r) << TC::A);           // workspace row r, columns col0..
-}
-
-// Tile (R rows x C columns, one plane) into LDS: column i in slot i, row r at
-// lds_index(r) of the slot.
-template <class TC>
-__device__ __forceinline__ void tile_in(const float* src, float* lds, int col0, int tid)
-{
-    constexpr int C4 = TC::C / 4;
-#pragma unroll
-    for (int c = 0; c < TC::E / 4; ++c) {
-        const int f4 = tid + c * TC::THREADS;
-        const int r = f4 / C4, c4 = f4 % C4;
-        const v4f v = load4<TC::PASS == 1>(src + tile_row_offset<TC>(r, col0) + 4 * c4);
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-            lds[(4 * c4 + e) * TC::SLOT + lds_index(r)] = v[e];
-    }
-}
-
-// Pass 1 output: block c of group i is contiguous in the workspace.
-template <class TC>
-__device__ __forceinline__ void blocks_out(float* dst, const float* lds, int col0, int tid)
-{
-    constexpr int R4 = TC::R / 4;
-#pragma unroll
-    for (int c = 0; c < TC::E / 4; ++c) {
-        const int f4 = tid + c * TC::THREADS;
-        const int i = f4 / R4, p4 = f4 % R4;
-        const float* s = lds + i * TC::SLOT + lds_index(4 * p4);
-        const int blk = rev_bits(col0 + i, TC::M - TC::A);
-        *reinterpret_cast<v4f*>(dst + static_cast<int64_t>(blk) * TC::R + 4 * p4) = v4f{s[0], s[1], s[2], s[3]};
-    }
-}
-
-// Pass 2 output: natural positions lo + (p << A), along tile rows.
-template <class TC>
-__device__ __forceinline__ void rows_out(float* dst, const float* lds, int col0, int tid)
-{
-    constexpr int C4 = TC::C / 4;
-#pragma unroll
-    for (int c = 0; c < TC::E / 4; ++c) {
-        const int f4 = tid + c * TC::THREADS;
-        const int r = f4 / C4, c4 = f4 % C4;
-        const float* s = lds + (4 * c4) * TC::SLOT + lds_index(r);
-        store4<true>(dst + tile_row_offset<TC>(r, col0) + 4 * c4,
-                     v4f{s[0], s[TC::SLOT], s[2 * TC::SLOT], s[3 * TC::SLOT]});
-    }
-}
-
-// Registers of the group's first local pass: position u + (t << RB); in
-// pass 1 that position is tile row rev_MA(position).
-template <class TC>
-__device__ __forceinline__ void tile_regs(float (&v)[TC::E], const float* slot, int t)
-{
-#pragma unroll
-    for (int u = 0; u < TC::E; ++u) {
-        if constexpr (TC::PASS == 1)
-            v[u] = slot[lds_index(rev_bits(t, TC::LT) + (rev_bits(u, TC::RB) << TC::LT))];
-        else
-            v[u] = slot[lds_index(u + (t << TC::RB))];
-    }
-}
-
-template <class TC>
-__device__ __forceinline__ void regs_tile(const float (&v)[TC::E], float* slot, int t)
-{
-    using Last = Pass<TC::MA, TC::RB, TC::NP - 1>;
-#pragma unroll
-    for (int u = 0; u < TC::E; ++u)
-        slot[lds_index(position<TC::LT, Last::S, Last::RP>(t, u))] = v[u];
-}
-
 template <class TC>
 __global__ void __launch_bounds__(TC::THREADS)
 split_fft_tile_kernel(const float* xr, const float* xi, float* yr, float* yi, const float2* __restrict__ tw,
                       int tiles_per_transform)
 {
-    constexpr int E = TC::E, LT = TC::LT, T = TC::T, C = TC::C;
     __shared__ float lds[TC::LDS_WORDS];
-    const int tid = threadIdx.x;
-    const int g = TC::GF ? tid % C : tid >> LT;  // group (column) within the tile
-    const int t = TC::GF ? tid / C : tid & (T - 1);
-    const int64_t b = blockIdx.x / tiles_per_transform;
-    const int col0 = (blockIdx.x % tiles_per_transform) * C;
-    const int64_t base = b * TC::N;
-    float* lr = lds + g * TC::SLOT;
-    float* li = TC::SPLIT ? lr : lr + C * TC::SLOT;
-    float* area_i = TC::SPLIT ? lds : lds + C * TC::SLOT;
-
-    float vr[E], vi[E];
-    tile_in<TC>(xr + base, lds, col0, tid);
-    if constexpr (TC::SPLIT) {
-        __syncthreads();
-        tile_regs<TC>(vr, lr, t);
-        __syncthreads();
-        tile_in<TC>(xi + base, lds, col0, tid);
-        __syncthreads();
-        tile_regs<TC>(vi, lr, t);
-    } else {
-        tile_in<TC>(xi + base, area_i, col0, tid);
-        __syncthreads();
-        tile_regs<TC>(vr, lr, t);
-        tile_regs<TC>(vi, li, t);
-    }
-    // the group's exchanges reuse its slot
-    __syncthreads();
-
-    const int lo_g = TC::PASS == 1 ? 0 : col0 + g;
-    stages<E, LT, 0, Pass<TC::MA, TC::RB, 0>::RP, 0, TC::TW_SHIFT>(vr, vi, t, tw, lo_g);
-    if constexpr (TC::NP > 1)
-        later_passes<TC::MA, TC::RB, 1, TC::SPLIT, E, 0, TC::TW_SHIFT, TC::GF ? 1024 : T>(vr, vi, lr, li, t, tw,
-                                                                                       lo_g);
-
-    // the group's slot is free again (its last exchange ended with a sync)
-    if constexpr (TC::SPLIT) {
-        regs_tile<TC>(vr, lr, t);
-        __syncthreads();
-        if constexpr (TC::PASS == 1)
-            blocks_out<TC>(yr + base, lds, col0, tid);
-        else
-            rows_out<TC>(yr + base, lds, col0, tid);
-        __syncthreads();
-        regs_tile<TC>(vi, lr, t);
-        __syncthreads();
-        if constexpr (TC::PASS == 1)
-            blocks_out<TC>(yi + base, lds, col0, tid);
-        else
-            rows_out<TC>(yi + base, lds, col0, tid);
-    } else {
-        regs_tile<TC>(vr, lr, t);
-        regs_tile<TC>(vi, li, t);
-        __syncthreads();
-        if constexpr (TC::PASS == 1) {
-            blocks_out<TC>(yr + base, lds, col0, tid);
-            blocks_out<TC>(yi + base, area_i, col0, tid);
-        } else {
-            rows_out<TC>(yr + base, lds, col0, tid);
-            rows_out<TC>(yi + base, area_i, col0, tid);
-        }
-    }
+    const int64_t base = static_cast<int64_t>(blockIdx.x / tiles_per_transform) * TC::N;
+    const int col0 = (blockIdx.x % tiles_per_transform) * TC::C;
+    tile_process<TC>(xr + base, xi + base, yr + base, yi + base, tw, col0, lds, threadIdx.x);
 }
 
 template <class TC>

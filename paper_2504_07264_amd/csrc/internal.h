@@ -4,7 +4,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 namespace splitdft {
+
+// The message split_dft_last_error() returns on this thread.
+void set_last_error(const std::string& msg);
 
 // One compiled single-pass kernel: transforms of length 2^m, 2^rb elements per
 // thread, tpw transforms per workgroup, plus data-movement options.
@@ -40,6 +45,42 @@ struct TwoPass {
 
 // Compiled two-pass schedules for length 2^m (count returned through *count).
 const TwoPass* two_pass_for(int m, int* count);
+
+// ---- grouped (ragged, mixed-length) execution --------------------------
+constexpr int kManyThreads = 512;         // workgroup size of the grouped kernel
+constexpr int kManyMinLog2N = 2;          // supported lengths 2^2 .. 2^16
+constexpr int kManyMaxLog2N = 16;
+constexpr int64_t kManyMaxN = int64_t{1} << kManyMaxLog2N;
+
+// One unit of work: `count` transforms of length 2^m taken from order[first..].
+struct ManyItem {
+    int32_t m;
+    int32_t dir;    // index into ManyArgs' plane pointers (0 or 1)
+    int32_t count;
+    int32_t pad;
+    int64_t first;
+};
+
+struct ManyArgs {
+    const float* in_r[2];
+    const float* in_i[2];
+    float* out_r[2];
+    float* out_i[2];
+    const int64_t* offsets;  // element offset of transform k in every plane
+    const int32_t* order;    // transform indices, grouped by length
+    const ManyItem* items;
+    int nitems;
+    int* queue;              // [0] next item, [1] workgroups finished
+    float* ws;               // per-workgroup intermediate: 2 * kManyMaxN floats each
+    const float2* tw;        // twiddle table of length 2^16 (its entries serve every length)
+};
+
+// Grouped-kernel builds: 0 = 128-VGPR budget (two workgroups per CU),
+// 1 = no register limit (one workgroup per CU).
+constexpr int kManyKernelVariants = 2;
+hipError_t launch_many(int variant, const ManyArgs& args, int grid, hipStream_t stream);
+hipError_t many_max_active_per_cu(int variant, int* blocks);
+int many_items_per_group(int m);
 
 // All compiled variants for length 2^m (count returned through *count).
 const Variant* variants_for(int m, int* count);

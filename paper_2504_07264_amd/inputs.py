@@ -59,3 +59,24 @@ def ragged_lengths(count: int = 20000, kmin: int = 4, kmax: int = 16, seed: int 
     g = torch.Generator().manual_seed(seed)
     k = torch.randint(kmin, kmax + 1, (count,), generator=g)
     return g, torch.pow(2, k).to(torch.int64)
+
+
+def draw_ragged(count: int = 20000, kmin: int = 4, kmax: int = 16, seed: int = 4, dist: str = "normal",
+                planes: int = 4):
+    """A ragged batch: lengths 2^k (k uniform on [kmin, kmax], drawn first),
+    then ``planes`` flat FP32 planes of sum(lengths) values each, drawn in
+    order from the same generator."""
+    g, lengths = ragged_lengths(count, kmin, kmax, seed)
+    total = int(lengths.sum())
+    out = []
+    for _ in range(planes):
+        if dist == "normal":
+            out.append(torch.randn(total, generator=g, dtype=torch.float32))
+        else:
+            out.append(torch.rand(total, generator=g, dtype=torch.float32) * 2.0 - 1.0)
+    return lengths, out
+
+
+# 20000 transforms of lengths 2^4 .. 2^16 (about 2^27.6 points), forward and
+# adjoint in one grouped launch
+RAGGED_COUNT, RAGGED_KMIN, RAGGED_KMAX, RAGGED_SEED = 20000, 4, 16, 4

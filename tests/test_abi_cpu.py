@@ -120,3 +120,29 @@ def test_product_path_does_not_reference_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "split_oracle" not in text and "liboracle" not in text, f
+
+
+def test_many_plan_validates_before_any_hip_call(L):
+    import numpy as np
+    h = ctypes.c_void_p()
+    for bad in ([4, 3], [1], [1 << 17], [0], [-16]):
+        a = np.asarray(bad, np.int64)
+        assert L.split_dft_many_plan(ctypes.byref(h), a.ctypes.data, a.size, 0) == 1
+    a = np.asarray([16, 32], np.int64)
+    assert L.split_dft_many_plan(ctypes.byref(h), a.ctypes.data, 0, 0) == 2
+    assert L.split_dft_many_plan(ctypes.byref(h), a.ctypes.data, 2, 1) == 6
+    assert L.split_dft_many_plan(ctypes.byref(h), a.ctypes.data, 2, 9 << 8) == 6
+    assert L.split_dft_many_plan(None, a.ctypes.data, 2, 0) == 3
+    assert L.split_dft_many_plan(ctypes.byref(h), None, 2, 0) == 3
+    bogus = ctypes.c_void_p(0x1000)
+    assert L.split_dft_many_exec(bogus, None, None, None, None, None) == 9
+    assert L.split_dft_graph_launch(bogus, None) == 9
+    assert L.split_dft_many_destroy(None) == 0 and L.split_dft_graph_destroy(None) == 0
+
+
+def test_ragged_generator_recipe():
+    from paper_2504_07264_amd import inputs
+    lengths, planes = inputs.draw_ragged(50, 4, 16, 4, planes=2)
+    assert len(lengths) == 50 and all(int(n) & (int(n) - 1) == 0 for n in lengths)
+    assert 16 <= int(lengths.min()) and int(lengths.max()) <= 65536
+    assert planes[0].numel() == int(lengths.sum()) == planes[1].numel()
