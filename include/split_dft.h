@@ -74,7 +74,13 @@ typedef enum {
                                needs |x| * 16 < 65504                            */
 #define SPLIT_DFT_BF16X3 3u /* bf16 hi+mid+lo, 6 products                       */
 /* Bits 8-15: 0 = default kernel schedule, k = compiled FP32 schedule k-1
- * (used by tuning); bits 16-31 must be 0. */
+ * (used by tuning). */
+/* Bit 24: evaluate through the decimation-in-frequency factorisation of
+ * eq. (9), y_2N = S D^(1) W^(1) ... D^(m) W^(m) x_2N (stages m down to 1,
+ * butterfly before rotation, the bit reversal last), FP32, n <= 2^13; results
+ * are bit-identical to those factors applied in that order with the
+ * operation forms above.  Other bits must be 0. */
+#define SPLIT_DFT_DIF (1u << 24)
 
 /* Largest supported log2 N. */
 #define SPLIT_DFT_MAX_LOG2N 16

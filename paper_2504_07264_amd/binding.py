@@ -31,6 +31,7 @@ BF16X2 = 1
 FP16X2 = 2
 BF16X3 = 3
 PRECISIONS = {"fp32": FP32, "bf16x2": BF16X2, "fp16x2": FP16X2, "bf16x3": BF16X3}
+DIF = 1 << 24  # decimation-in-frequency factorisation (eq. 9)
 MAX_LOG2N = 16
 
 EXPORTED = (

@@ -184,23 +184,27 @@ split_dft_status split_dft_plan(split_dft_plan_t* out, int64_t n, int64_t batch,
         return fail(SPLIT_DFT_ERR_INVALID_BATCH, "n * batch * 4 bytes overflows int64");
     const uint32_t precision = flags & 0xffu;
     const uint32_t vsel = (flags >> 8) & 0xffu;  // 0 = default schedule, k = compiled schedule k-1
-    if (precision > SPLIT_DFT_BF16X3 || (flags >> 16) != 0)
+    const bool dif = (flags & SPLIT_DFT_DIF) != 0;
+    if (precision > SPLIT_DFT_BF16X3 || ((flags & ~SPLIT_DFT_DIF) >> 16) != 0)
         return fail(SPLIT_DFT_ERR_UNSUPPORTED, "unsupported flags " + std::to_string(flags));
     const int mode = static_cast<int>(precision);
-    if (mode != splitdft::kModeFP32 && (m != 8 || vsel != 0))
-        return fail(SPLIT_DFT_ERR_UNSUPPORTED, "matrix-core precision modes support n = 256 only");
+    if (mode != splitdft::kModeFP32 && (m != 8 || vsel != 0 || dif))
+        return fail(SPLIT_DFT_ERR_UNSUPPORTED, "matrix-core precision modes support n = 256 (DIT) only");
 
     // schedules: the compiled single-pass variants, then the two-pass ones;
     // selector 0 = the default for the length
     int count = 0, count2 = 0;
-    const splitdft::Variant* list = splitdft::variants_for(m, &count);
-    const splitdft::TwoPass* list2 = splitdft::two_pass_for(m, &count2);
+    const splitdft::Variant* list =
+        dif ? splitdft::dif_variants_for(m, &count) : splitdft::variants_for(m, &count);
+    const splitdft::TwoPass* list2 = dif ? nullptr : splitdft::two_pass_for(m, &count2);
+    if (dif && count == 0)
+        return fail(SPLIT_DFT_ERR_UNSUPPORTED, "the decimation-in-frequency schedule supports n <= 2^13");
     const splitdft::Variant* v = nullptr;
     const splitdft::TwoPass* two = nullptr;
     if (vsel == 0) {
         if (mode != splitdft::kModeFP32 || count > 0)
-            v = splitdft::default_variant(m, batch);
-        if (m >= kTwoPassDefaultLog2N || !v)
+            v = dif ? &list[0] : splitdft::default_variant(m, batch);
+        if (!dif && (m >= kTwoPassDefaultLog2N || !v))
             two = count2 > 0 ? &list2[0] : nullptr;
         if (two)
             v = nullptr;
@@ -401,7 +405,8 @@ split_dft_status split_dft_plan_describe(split_dft_plan_t plan, char* buf, size_
         return SPLIT_DFT_OK;
     }
     const splitdft::Variant* v = plan->variant;
-    std::snprintf(buf, len, "ept=%d tpw=%d threads=%d lds=%d split=%d nt=%d twl=%d wpe=%d f4io=%d", 1 << v->rb,
+    std::snprintf(buf, len, "%sept=%d tpw=%d threads=%d lds=%d split=%d nt=%d twl=%d wpe=%d f4io=%d",
+                  (plan->flags & SPLIT_DFT_DIF) ? "dif " : "", 1 << v->rb,
                   v->tpw, v->threads, v->lds_bytes, v->split ? 1 : 0, v->nt ? 1 : 0, v->twl ? 1 : 0, v->wpe,
                   v->f4io ? 1 : 0);
     return SPLIT_DFT_OK;

@@ -96,6 +96,49 @@ __device__ __forceinline__ void stages(float (&vr)[E], float (&vi)[E], int t, co
     }
 }
 
+// Stages S+RP .. S+1 of the decimation-in-frequency factorisation, eq. (9),
+// on the E registers of one thread (positions as in the DIT passes): for each
+// stage, highest first, the butterfly W^(i) (u + v, u - v) and then the
+// rotation D^(i) of the upper element by omega^(i,q), q as in stages().
+template <int E, int LT, int S, int RP>
+__device__ __forceinline__ void stages_dif(float (&vr)[E], float (&vi)[E], int t, const float2* __restrict__ tw)
+{
+#pragma unroll
+    for (int k = RP; k >= 1; --k) {
+        const int half = 1 << (k - 1);
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            if (u & half)
+                continue;
+            const int v = u + half;
+            const float ur = vr[u], ui = vi[u], wr = vr[v], wi = vi[v];
+            vr[u] = ur + wr;
+            vi[u] = ui + wi;
+            float dr = ur - wr, di = ui - wi;
+            if constexpr (S == 0) {
+                const int q = u & (half - 1);
+                if (q == 0) {
+                    // omega^(k,0) = I
+                } else if (2 * q == half) {
+                    const float tr = di;  // angle pi/2
+                    di = -dr;
+                    dr = tr;
+                } else {
+                    const float2 w = tw[half + q];
+                    rotate(dr, di, w.x, w.y);
+                }
+            } else {
+                const int o = t + ((u >> RP) << LT);
+                const int q = (o & ((1 << S) - 1)) + ((u & (half - 1)) << S);
+                const float2 w = tw[(1 << (S + k - 1)) + q];
+                rotate(dr, di, w.x, w.y);
+            }
+            vr[v] = dr;
+            vi[v] = di;
+        }
+    }
+}
+
 // Orders a wave's LDS writes before its later LDS reads by other lanes of the
 // same wave (LDS operations of one wave complete in order).
 __device__ __forceinline__ void wave_lds_sync()
@@ -136,6 +179,49 @@ __device__ __forceinline__ void lds_get(float (&v)[E], const float* lds, int t)
 #pragma unroll
     for (int u = 0; u < E; ++u)
         v[u] = lds[lds_index(position<LT, S1, RP1>(t, u))];
+}
+
+// Passes of the decimation-in-frequency order: pass 0 covers the top RP0
+// bits (RP0 = M - RB (NP - 1), the partial one), later passes RB bits each,
+// downwards, the last one bits 0 .. RB-1.
+template <int M, int RB, int P>
+struct PassD {
+    static constexpr int NP = (M + RB - 1) / RB;
+    static constexpr int RP0 = M - RB * (NP - 1);
+    static constexpr int RP = P == 0 ? RP0 : RB;
+    static constexpr int S = M - RP0 - RB * P;
+};
+
+// DIF passes P, P+1, ...: exchange through LDS, then the pass's stages.
+template <int M, int RB, int P, bool SPLIT, int E>
+__device__ __forceinline__ void later_passes_dif(float (&vr)[E], float (&vi)[E], float* lr, float* li, int t,
+                                                 const float2* __restrict__ tw)
+{
+    if constexpr (P < PassD<M, RB, 0>::NP) {
+        constexpr int LT = M - RB;
+        constexpr int T = 1 << LT;
+        using Prev = PassD<M, RB, P - 1>;
+        using Cur = PassD<M, RB, P>;
+        if constexpr (SPLIT) {
+            lds_put<E, LT, Prev::S, Prev::RP, Cur::S, Cur::RP>(vr, lr, t);
+            xsync<T>();
+            lds_get<E, LT, Cur::S, Cur::RP>(vr, lr, t);
+            xsync<T>();
+            lds_put<E, LT, Prev::S, Prev::RP, Cur::S, Cur::RP>(vi, lr, t);
+            xsync<T>();
+            lds_get<E, LT, Cur::S, Cur::RP>(vi, lr, t);
+            xsync<T>();
+        } else {
+            lds_put<E, LT, Prev::S, Prev::RP, Cur::S, Cur::RP>(vr, lr, t);
+            lds_put<E, LT, Prev::S, Prev::RP, Cur::S, Cur::RP>(vi, li, t);
+            xsync<T>();
+            lds_get<E, LT, Cur::S, Cur::RP>(vr, lr, t);
+            lds_get<E, LT, Cur::S, Cur::RP>(vi, li, t);
+            xsync<T>();
+        }
+        stages_dif<E, LT, Cur::S, Cur::RP>(vr, vi, t, tw);
+        later_passes_dif<M, RB, P + 1, SPLIT, E>(vr, vi, lr, li, t, tw);
+    }
 }
 
 // Passes P, P+1, ... of a group of 2^M positions: exchange through LDS, then

@@ -283,6 +283,101 @@ split_fft_lds_kernel(const float* xr, const float* xi, float* yr, float* yi, con
     }
 }
 
+// Decimation-in-frequency schedule (eq. 9): natural-order loads of the first
+// pass's positions, stages m down to 1 (butterfly, then rotation), and the
+// bit reversal S applied last, folded into the store addresses.  In the last
+// pass (bits 0 .. RB-1) position u + (t << RB) goes to output
+// rev_M(u + (t << RB)) = (rev_RB(u) << LT) + rev_LT(t): coalesced over t.
+template <class C>
+__global__ void __launch_bounds__(C::THREADS) __attribute__((amdgpu_waves_per_eu(C::WPE)))
+split_fft_dif_kernel(const float* xr, const float* xi, float* yr, float* yi, const float2* __restrict__ tw,
+                     int64_t batch)
+{
+    constexpr int M = C::M, RB = C::RB, TPW = C::TPW;
+    constexpr int N = C::N, E = C::E, LT = C::LT, T = C::T, NP = C::NP;
+    constexpr bool NT = C::NT;
+    __shared__ float lds[C::XCH_WORDS];
+    const int tid = threadIdx.x;
+    const int slot = tid >> LT;
+    const int t = tid & (T - 1);
+    const int64_t b = static_cast<int64_t>(blockIdx.x) * TPW + slot;
+    const bool active = b < batch;
+    const int64_t row = b * N;
+    float* lr = lds + slot * C::SLOT;
+    float* li = C::SPLIT ? lr : lr + TPW * C::SLOT;
+    using First = PassD<M, RB, 0>;
+
+    float vr[E], vi[E];
+    if constexpr (T == 1 && N >= 4) {
+        if (active) {
+#pragma unroll
+            for (int c = 0; c < N / 4; ++c) {
+                const v4f a = load4<NT>(xr + row + 4 * c), z = load4<NT>(xi + row + 4 * c);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    vr[4 * c + e] = a[e];
+                    vi[4 * c + e] = z[e];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < E; ++u)
+                vr[u] = vi[u] = 0.0f;
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            const int64_t idx = row + position<LT, First::S, First::RP>(t, u);
+            vr[u] = active ? load1<NT>(xr + idx) : 0.0f;
+            vi[u] = active ? load1<NT>(xi + idx) : 0.0f;
+        }
+    }
+
+    stages_dif<E, LT, First::S, First::RP>(vr, vi, t, tw);
+    if constexpr (NP > 1)
+        later_passes_dif<M, RB, 1, C::SPLIT, E>(vr, vi, lr, li, t, tw);
+
+    if (!active)
+        return;
+    if constexpr (T == 1 && N >= 4) {
+#pragma unroll
+        for (int c = 0; c < N / 4; ++c) {
+            store4<NT>(yr + row + 4 * c, v4f{vr[rev_bits(4 * c, M)], vr[rev_bits(4 * c + 1, M)],
+                                             vr[rev_bits(4 * c + 2, M)], vr[rev_bits(4 * c + 3, M)]});
+            store4<NT>(yi + row + 4 * c, v4f{vi[rev_bits(4 * c, M)], vi[rev_bits(4 * c + 1, M)],
+                                             vi[rev_bits(4 * c + 2, M)], vi[rev_bits(4 * c + 3, M)]});
+        }
+    } else {
+        const int tb = rev_bits(t, LT);
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            const int64_t idx = row + (rev_bits(u, RB) << LT) + tb;
+            store1<NT>(yr + idx, vr[u]);
+            store1<NT>(yi + idx, vi[u]);
+        }
+    }
+}
+
+template <class C>
+hipError_t launch_dif(const float* xr, const float* xi, float* yr, float* yi, const float2* tw, int64_t batch,
+                      hipStream_t stream)
+{
+    const int64_t blocks = (batch + C::TPW - 1) / C::TPW;
+    if (blocks > INT_MAX)
+        return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(split_fft_dif_kernel<C>, dim3(static_cast<unsigned>(blocks)), dim3(C::THREADS), 0, stream,
+                       xr, xi, yr, yi, tw, batch);
+    return hipGetLastError();
+}
+
+template <int M, int RB, int TPW, bool SPLIT, bool NT, int WPE>
+constexpr Variant D()
+{
+    using C = Cfg<M, RB, TPW, SPLIT, NT, false, WPE>;
+    return Variant{C::M, C::RB, C::TPW, C::THREADS, C::LDS_BYTES, C::SPLIT, C::NT, false, C::WPE, false,
+                   &launch_dif<C>};
+}
+
 // N = 1: the transform is the identity.
 __global__ void __launch_bounds__(256) split_fft_len1_kernel(const float* xr, const float* xi, float* yr, float* yi,
                                                              int64_t batch)
@@ -369,7 +464,39 @@ const VariantList kLists[] = {SDFT_L(kV0),  SDFT_L(kV1),  SDFT_L(kV2),  SDFT_L(k
                               SDFT_L(kV12), SDFT_L(kV13), SDFT_L(kV14), SDFT_L(kV15)};
 #undef SDFT_L
 
+// decimation-in-frequency schedules
+//                      M   RB TPW SPLIT NT WPE
+const Variant kD1[] = {D<1, 1, 256, false, false, 1>()};
+const Variant kD2[] = {D<2, 2, 256, false, false, 1>()};
+const Variant kD3[] = {D<3, 3, 256, false, false, 1>()};
+const Variant kD4[] = {D<4, 4, 64, false, false, 1>()};
+const Variant kD5[] = {D<5, 4, 64, false, false, 1>()};
+const Variant kD6[] = {D<6, 4, 32, false, false, 1>()};
+const Variant kD7[] = {D<7, 4, 16, false, false, 1>()};
+const Variant kD8[] = {D<8, 4, 16, true, false, 4>()};
+const Variant kD9[] = {D<9, 4, 8, true, true, 4>()};
+const Variant kD10[] = {D<10, 4, 4, true, true, 4>()};
+const Variant kD11[] = {D<11, 4, 2, true, true, 4>()};
+const Variant kD12[] = {D<12, 4, 1, true, true, 4>()};
+const Variant kD13[] = {D<13, 4, 1, true, true, 4>()};
+
+#define SDFT_L(a) VariantList{a, static_cast<int>(sizeof(a) / sizeof(a[0]))}
+const VariantList kDLists[] = {SDFT_L(kV0),  SDFT_L(kD1),  SDFT_L(kD2),  SDFT_L(kD3), SDFT_L(kD4),
+                               SDFT_L(kD5),  SDFT_L(kD6),  SDFT_L(kD7),  SDFT_L(kD8), SDFT_L(kD9),
+                               SDFT_L(kD10), SDFT_L(kD11), SDFT_L(kD12), SDFT_L(kD13)};
+#undef SDFT_L
+
 }  // namespace
+
+const Variant* dif_variants_for(int m, int* count)
+{
+    if (m < 0 || m >= static_cast<int>(sizeof(kDLists) / sizeof(kDLists[0]))) {
+        *count = 0;
+        return nullptr;
+    }
+    *count = kDLists[m].count;
+    return kDLists[m].v;
+}
 
 const Variant* variants_for(int m, int* count)
 {

@@ -85,6 +85,9 @@ int many_items_per_group(int m);
 // All compiled variants for length 2^m (count returned through *count).
 const Variant* variants_for(int m, int* count);
 
+// Compiled decimation-in-frequency (eq. 9) variants for length 2^m, m <= 13.
+const Variant* dif_variants_for(int m, int* count);
+
 // Default variant for a length and batch.
 const Variant* default_variant(int m, int64_t batch);
 

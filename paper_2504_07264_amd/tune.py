@@ -1,0 +1,187 @@
+"""Autotuner for kernel schedules.
+
+Every length has several compiled schedules (elements per thread, transforms
+per workgroup, LDS exchange form, 16-byte staging, two-pass tiling), and the
+grouped kernel has two builds and a workgroups-per-CU setting.  The tuner
+times each candidate on the current device with HIP events over rotating
+buffers and records the fastest in a JSON cache keyed by the device (name,
+CU count) and the library build; plans created with ``schedule="tuned"``
+(``tuned_plan``) look the choice up there.
+
+Command line:
+    python -m paper_2504_07264_amd.tune --lengths 16,256,1024,4096,65536 \\
+        --points 16777216 [--ragged 20000] [--cache PATH]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import threading
+
+import torch
+
+from . import binding
+from .binding import ManyPlan, Plan, SplitDFTError, many_flags, variant_flag
+
+_cache_lock = threading.Lock()
+
+
+def cache_path() -> str:
+    p = os.environ.get("SPLIT_DFT_TUNE_CACHE")
+    if p:
+        return p
+    return os.path.join(os.path.expanduser("~"), ".cache", "splitdft", "tune.json")
+
+
+def device_key(device=None) -> str:
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    props = torch.cuda.get_device_properties(dev)
+    with open(binding.LIB_PATH, "rb") as f:
+        lib_hash = hashlib.sha256(f.read()).hexdigest()[:16]
+    arch = getattr(props, "gcnArchName", "gfx")
+    return "%s|%s|cu%d|lib%s" % (props.name, arch, props.multi_processor_count, lib_hash)
+
+
+def load_cache(path=None) -> dict:
+    path = path or cache_path()
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(data: dict, path=None) -> None:
+    path = path or cache_path()
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def _time(fn, iters: int, warmup: int = 3) -> float:
+    """Median microseconds of fn(k) over ``iters`` launches (HIP events)."""
+    for k in range(warmup):
+        fn(k)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(iters)]
+    for k in range(iters):
+        ev[k][0].record()
+        fn(k)
+        ev[k][1].record()
+    torch.cuda.synchronize()
+    t = sorted(a.elapsed_time(b) for a, b in ev)
+    return t[len(t) // 2] * 1e3
+
+
+def schedules(n: int):
+    """Flag values of every compiled FP32 schedule for length n."""
+    out = []
+    k = 0
+    while True:
+        try:
+            with Plan(n, 1, variant_flag(k)):
+                pass
+        except SplitDFTError:
+            return out
+        out.append(variant_flag(k))
+        k += 1
+
+
+def tune_length(n: int, batch: int, iters: int = 20, sets: int = 3):
+    """Time every compiled schedule for (n, batch); returns (best flags, timings)."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    bufs = [tuple(torch.randn(batch, n, device=dev) for _ in range(4)) for _ in range(sets)]
+    timings = {}
+    for flags in schedules(n):
+        with Plan(n, batch, flags) as p:
+            us = _time(lambda k: p.exec(*bufs[k % sets]), iters)
+            timings[flags] = {"us": round(us, 2), "schedule": p.describe()}
+    best = min(timings, key=lambda f: timings[f]["us"])
+    return best, timings
+
+
+def tune_many(lengths, iters: int = 5):
+    """Time the grouped kernel builds and workgroups-per-CU settings on a
+    forward + adjoint graph of the ragged batch; returns (best flags, timings)."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    total = int(sum(int(n) for n in lengths))
+    planes = [torch.randn(total, device=dev) for _ in range(8)]
+    timings = {}
+    for build in range(2):
+        for wpc in (0, 1):
+            flags = many_flags(build, wpc)
+            with ManyPlan(lengths, flags) as p:
+                g = p.graph(*planes)
+                us = _time(lambda k: g.launch(), iters, warmup=1)
+                g.close()
+                timings[flags] = {"us": round(us, 1), "workgroups": p.info()["workgroups"]}
+    best = min(timings, key=lambda f: timings[f]["us"])
+    return best, timings
+
+
+def ragged_key(lengths) -> str:
+    h = hashlib.sha256(torch.as_tensor(list(lengths), dtype=torch.int64).numpy().tobytes()).hexdigest()[:16]
+    return "ragged:%d:%s" % (len(lengths), h)
+
+
+def record(key: str, flags: int, timings: dict, path=None) -> None:
+    with _cache_lock:
+        data = load_cache(path)
+        dk = device_key()
+        data.setdefault(dk, {})[key] = {"flags": int(flags),
+                                        "timings": {str(k): v for k, v in timings.items()}}
+        save_cache(data, path)
+
+
+def lookup(key: str, path=None):
+    """Tuned flags for ``key`` on this device and library build, or None."""
+    data = load_cache(path)
+    entry = data.get(device_key(), {}).get(key)
+    return None if entry is None else int(entry["flags"])
+
+
+def length_key(n: int, batch: int) -> str:
+    return "length:%d:%d" % (n, batch)
+
+
+def tuned_plan(n: int, batch: int, path=None) -> Plan:
+    """A plan with the cached fastest schedule (default schedule if untuned)."""
+    flags = lookup(length_key(n, batch), path)
+    return Plan(n, batch, 0 if flags is None else flags)
+
+
+def tuned_many_plan(lengths, path=None) -> ManyPlan:
+    flags = lookup(ragged_key(lengths), path)
+    return ManyPlan(lengths, 0 if flags is None else flags)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--lengths", default="16,256,1024,4096,65536")
+    ap.add_argument("--points", type=int, default=1 << 24, help="points per length (batch = points / n)")
+    ap.add_argument("--ragged", type=int, default=0, help="also tune the ragged workload of this many transforms")
+    ap.add_argument("--cache", default=None)
+    ap.add_argument("--iters", type=int, default=20)
+    args = ap.parse_args(argv)
+    for n in [int(x) for x in args.lengths.split(",") if x]:
+        batch = max(1, args.points // n)
+        best, t = tune_length(n, batch, args.iters)
+        record(length_key(n, batch), best, t, args.cache)
+        print(json.dumps({"n": n, "batch": batch, "best_flags": best, "best": t[best], "candidates": len(t)}),
+              flush=True)
+    if args.ragged:
+        from . import inputs
+
+        lengths, _ = inputs.ragged_lengths(args.ragged, inputs.RAGGED_KMIN, inputs.RAGGED_KMAX, inputs.RAGGED_SEED)
+        lengths = lengths.tolist()
+        best, t = tune_many(lengths)
+        record(ragged_key(lengths), best, t, args.cache)
+        print(json.dumps({"ragged": args.ragged, "best_flags": best, "timings": t}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

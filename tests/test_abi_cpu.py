@@ -67,6 +67,12 @@ def test_matrix_core_modes_need_n256(L, n, mode):
     assert st == 6 and h.value is None
 
 
+def test_dif_flag_domain(L):
+    assert _plan(L, 1 << 14, 4, binding.DIF)[0] == 6
+    assert _plan(L, 256, 4, binding.DIF | binding.BF16X2)[0] == 6
+    assert _plan(L, 256, 4, binding.DIF | (1 << 25))[0] == 6
+
+
 def test_plan_null_out(L):
     assert L.split_dft_plan(None, 16, 1, 0) == 3
 

@@ -265,3 +265,20 @@ def test_two_pass_chunks_and_caller_workspace():
 def test_single_pass_plans_need_no_workspace():
     with Plan(1024, 8) as p:
         assert p.workspace_bytes() == 0
+
+
+# ------------------------------------------------------- decimation in frequency (eq. 9)
+@pytest.mark.parametrize("m", range(0, 14))
+def test_dif_every_length(m):
+    n = 1 << m
+    batch = max(3, min(1000, (1 << 19) // n)) | 1
+    xr, xi = inputs.draw_planes(n, batch, "normal", 3000 + m)
+    yr, yi = gpu_exec(n, batch, xr, xi, binding.DIF)
+    mr, mi = oracle.split_fft_dif_f32(xr.numpy(), xi.numpy())
+    assert_bit_exact(yr, yi, mr, mi)
+    rr, ri = oracle.split_fft(xr.double().numpy(), xi.double().numpy())
+    assert_within_tol(yr, yi, rr, ri, n)
+    # the adjoint through the plane exchange
+    ar, ai = gpu_exec(n, batch, xr, xi, binding.DIF, adjoint=True)
+    hr, hi = oracle.split_fft_dif_f32(xi.numpy(), xr.numpy())
+    assert_bit_exact(ar, ai, hi, hr)
