@@ -170,6 +170,69 @@ def mfma_vs_fp32(steps: int = 50, sets: int = 4):
     return out
 
 
+def grad_n4096(steps: int = 30, sets: int = 3):
+    """Forward + adjoint (the autograd step's two kernels) at N=4096 x 4096."""
+    import torch
+
+    from paper_2504_07264_amd import Plan, inputs
+
+    w = inputs.GRAD_N4096
+    xr, xi, wr, wi = inputs.draw(w)
+    dev = torch.device("cuda", 0)
+    bufs = [tuple(t.to(dev) for t in (xr, xi, wr, wi)) + tuple(torch.empty(w.batch, w.n, device=dev)
+                                                             for _ in range(4)) for _ in range(sets)]
+    with Plan(w.n, w.batch) as plan:
+        def step(k):
+            a, b, c, d, yr, yi, gr, gi = bufs[k % sets]
+            plan.exec(a, b, yr, yi)
+            plan.adjoint(c, d, gr, gi)
+
+        for k in range(3):
+            step(k)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for k in range(steps):
+            step(k)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        return {"workload": "split_fft_n4096_b4096 forward + adjoint", "ms_per_step": round(ms, 4),
+                "GBps": round(2 * 16 * w.n * w.batch / ms / 1e6, 1), "schedule": plan.describe()}
+
+
+def ragged_grouped(reps: int = 10):
+    """20000 transforms of lengths 2^4..2^16, forward + adjoint, one
+    persistent launch replayed from a captured HIP graph."""
+    import torch
+
+    from paper_2504_07264_amd import ManyPlan, inputs
+
+    lengths, planes = inputs.draw_ragged(inputs.RAGGED_COUNT, inputs.RAGGED_KMIN, inputs.RAGGED_KMAX,
+                                         inputs.RAGGED_SEED)
+    dev = torch.device("cuda", 0)
+    total = int(lengths.sum())
+    xr, xi, gr, gi = [t.to(dev) for t in planes]
+    del planes
+    out = [torch.empty(total, device=dev) for _ in range(4)]
+    with ManyPlan(lengths.numpy()) as plan:
+        g = plan.graph(xr, xi, out[0], out[1], gr, gi, out[2], out[3])
+        g.launch()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            g.launch()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        info = plan.info()
+        g.close()
+    return {"workload": "20000 transforms, lengths 2^4..2^16 (k uniform, seed 4), forward + adjoint, one graph",
+            "points": total, "ms_per_launch": round(ms, 4), "GBps": round(32 * total / ms / 1e6, 1),
+            "workgroups": info["workgroups"], "items": info["items"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,6 +240,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mfma", action="store_true", help="skip the matrix-core comparison")
+    ap.add_argument("--no-extra", action="store_true", help="skip the N=4096 and ragged side reports")
     ap.add_argument("--counters", action="store_true",
                     help="only launch the forward kernel and a calibration copy (for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -279,10 +343,16 @@ def main():
         },
         "device": torch.cuda.get_device_name(dev),
     }
+    del sets
+    torch.cuda.empty_cache()
     if not args.no_mfma:
-        del sets
-        torch.cuda.empty_cache()
         out["mfma_vs_fp32"] = mfma_vs_fp32()
+        torch.cuda.empty_cache()
+    if not args.no_extra:
+        out["grad_n4096"] = grad_n4096()
+        torch.cuda.empty_cache()
+        out["ragged_grouped"] = ragged_grouped()
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(xr, xi, gr, gi)
     plan.close()

@@ -443,12 +443,11 @@ const Variant kV8[] = {V<8, 4, 16, Y, Y, Y, 4, Y>(), V<8, 4, 16, _, Y, Y, 1, Y>(
                        V<8, 4, 32, Y, Y, Y, 4, Y>()};
 const Variant kV9[] = {V<9, 4, 8, Y, Y, Y, 4, Y>(), V<9, 4, 8, _, Y, Y, 1>(), V<9, 4, 8, _, Y, Y, 1, Y>(),
                        V<9, 4, 16, Y, Y, Y, 4, Y>()};
-const Variant kV10[] = {V<10, 4, 4, Y, Y, Y, 4>(),    V<10, 4, 4, Y, Y, Y, 4, Y>(), V<10, 4, 4, _, Y, Y, 4, Y>(),
-                        V<10, 5, 8, Y, Y, Y, 1, Y>(), V<10, 5, 8, Y, Y, Y, 1>(),    V<10, 4, 8, Y, Y, Y, 4, Y>(),
-                        V<10, 4, 8, Y, Y, Y, 4>(),    V<10, 4, 16, Y, Y, Y, 4>(),   V<10, 4, 16, Y, Y, Y, 8>()};
+const Variant kV10[] = {V<10, 4, 8, Y, Y, Y, 4>(),    V<10, 4, 4, Y, Y, Y, 4>(),    V<10, 4, 4, Y, Y, Y, 4, Y>(),
+                        V<10, 5, 8, Y, Y, Y, 1>(),    V<10, 4, 8, Y, Y, Y, 4, Y>(), V<10, 4, 16, Y, Y, Y, 4>()};
 const Variant kV11[] = {V<11, 5, 4, Y, Y, Y, 1>(), V<11, 4, 2, Y, Y, Y, 4, Y>(), V<11, 5, 4, Y, Y, Y, 1, Y>()};
-const Variant kV12[] = {V<12, 5, 2, _, Y, _, 1>(), V<12, 5, 2, Y, Y, Y, 1>(), V<12, 4, 1, Y, Y, _, 4>(),
-                        V<12, 4, 2, Y, Y, _, 4>(),  V<12, 4, 1, Y, Y, Y, 4, Y>()};
+const Variant kV12[] = {V<12, 5, 2, Y, Y, Y, 2>(), V<12, 5, 2, _, Y, _, 1>(), V<12, 5, 2, Y, Y, Y, 1>(),
+                        V<12, 4, 2, Y, Y, Y, 4>(), V<12, 4, 1, Y, Y, Y, 4, Y>()};
 const Variant kV13[] = {V<13, 5, 1, _, Y, _, 1>(), V<13, 5, 1, Y, Y, _, 1, Y>()};
 const Variant kV14[] = {V<14, 5, 1, _, Y, _, 1>(), V<14, 5, 1, Y, Y, _, 1>()};
 const Variant kV15[] = {V<15, 5, 1, Y, Y, _, 1>()};
