@@ -138,8 +138,16 @@ def twiddle_table(m: int):
     return c, s
 
 
-def _stream_handle(device: torch.device) -> int:
-    return torch.cuda.current_stream(device).cuda_stream
+_raw_stream = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+
+
+def _stream_handle(device) -> int:
+    """The current stream of ``device`` (a torch.device or an index) as a raw
+    hipStream_t value."""
+    index = device if isinstance(device, int) else device.index
+    if _raw_stream is not None:
+        return _raw_stream(index)
+    return torch.cuda.current_stream(index).cuda_stream
 
 
 class Plan:
@@ -152,10 +160,14 @@ class Plan:
         self.flags = int(flags)
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
             else torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             check(L.split_dft_plan(ctypes.byref(h), self.n, self.batch, self.flags))
         self._h = h
+        self._index = self.device.index
+        self._numel = self.n * self.batch
 
     @property
     def handle(self):
@@ -177,13 +189,14 @@ class Plan:
         return int(lib().split_dft_workspace_bytes(self._h))
 
     def _check_plane(self, t: torch.Tensor, name: str) -> None:
+        # cheap attribute checks only: this runs four times per launch
         if not isinstance(t, torch.Tensor):
             raise TypeError("%s must be a torch.Tensor" % name)
-        if t.dtype != torch.float32:
+        if t.dtype is not torch.float32:
             raise TypeError("%s must be float32, got %s" % (name, t.dtype))
-        if t.device != self.device:
+        if not t.is_cuda or t.get_device() != self._index:
             raise ValueError("%s is on %s, the plan on %s" % (name, t.device, self.device))
-        if t.numel() != self.n * self.batch or (t.dim() >= 1 and t.shape[-1] != self.n):
+        if t.numel() != self._numel or (t.dim() >= 1 and t.shape[-1] != self.n):
             raise ValueError("%s must hold [batch=%d, n=%d] floats, got shape %s"
                              % (name, self.batch, self.n, tuple(t.shape)))
         if not t.is_contiguous():
@@ -198,9 +211,13 @@ class Plan:
             out_i = torch.empty_like(ai)
         self._check_plane(out_r, "output real")
         self._check_plane(out_i, "output imag")
-        with torch.cuda.device(self.device):
-            check(fn(self._h, ar.data_ptr(), ai.data_ptr(), out_r.data_ptr(), out_i.data_ptr(),
-                     _stream_handle(self.device)))
+        args = (self._h, ar.data_ptr(), ai.data_ptr(), out_r.data_ptr(), out_i.data_ptr(),
+                _stream_handle(self._index))
+        if torch.cuda.current_device() == self._index:
+            check(fn(*args))
+        else:
+            with torch.cuda.device(self._index):
+                check(fn(*args))
         return out_r, out_i
 
     def exec(self, xr, xi, yr=None, yi=None):

@@ -33,9 +33,10 @@ namespace {
 
 thread_local std::string g_last_error;
 
-// Lengths from 2^14 up use the two-pass schedule by default (measured faster
-// than the single-workgroup kernels, which hold one transform per CU).
-constexpr int kTwoPassDefaultLog2N = 14;
+// Length 2^16 uses the two-pass schedule by default: one transform (512 KiB)
+// does not fit a CU's LDS and registers.  Lengths up to 2^15 run in a single
+// pass (measured faster than two passes, which move the data twice).
+constexpr int kTwoPassDefaultLog2N = 16;
 // Workspace per two-pass chunk (both planes); measured on MI355X, chunks of
 // 128 MiB beat smaller ones (fewer, larger launches).
 constexpr int64_t kTwoPassChunkBytes = int64_t{128} << 20;
@@ -405,10 +406,10 @@ split_dft_status split_dft_plan_describe(split_dft_plan_t plan, char* buf, size_
         return SPLIT_DFT_OK;
     }
     const splitdft::Variant* v = plan->variant;
-    std::snprintf(buf, len, "%sept=%d tpw=%d threads=%d lds=%d split=%d nt=%d twl=%d wpe=%d f4io=%d",
+    std::snprintf(buf, len, "%sept=%d tpw=%d threads=%d lds=%d split=%d nt=%d twl=%d wpe=%d f4io=%d%s",
                   (plan->flags & SPLIT_DFT_DIF) ? "dif " : "", 1 << v->rb,
-                  v->tpw, v->threads, v->lds_bytes, v->split ? 1 : 0, v->nt ? 1 : 0, v->twl ? 1 : 0, v->wpe,
-                  v->f4io ? 1 : 0);
+                  v->tpw, v->threads, v->lds_bytes, v->split ? 1 : 0, v->nt ? 1 : 0, v->twl, v->wpe,
+                  v->f4io, v->pf ? " persistent" : "");
     return SPLIT_DFT_OK;
 }
 

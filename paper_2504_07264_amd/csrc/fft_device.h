@@ -49,13 +49,42 @@ __device__ __forceinline__ void rotate(float& ar, float& ai, float c, float s)
     ai = ti;
 }
 
+// Twiddle sources: omega^(i,q) for stage i ("level") and index q < 2^(i-1).
+//
+// TwTable<OFF>: the plan's table, entry 2^(i-1) + q read at tw[entry - OFF]
+// (OFF > 0 when only the upper part of the table is staged).
+template <int OFF>
+struct TwTable {
+    static __device__ __forceinline__ float2 get(const float2* __restrict__ tw, int level, int q)
+    {
+        return tw[(1 << (level - 1)) - OFF + q];
+    }
+};
+
+// TwQuarter<MQ>: only the first quarter turn of stage MQ's twiddles,
+// tw[k] = omega^(MQ, k) for k < 2^(MQ-2).  omega^(i,q) has the angle of
+// omega^(MQ, q 2^(MQ-i)) and the table holds the same FP32 value for equal
+// angles; an angle a + pi/2 in the upper quarter has (cos, sin) =
+// (-sin a, cos a), which the table's quadrant rule also gives exactly (with
+// +0 for -0, hence 0 - s rather than a negation).
+template <int MQ>
+struct TwQuarter {
+    static __device__ __forceinline__ float2 get(const float2* __restrict__ tw, int level, int q)
+    {
+        constexpr int H = 1 << (MQ - 2);
+        const int idx = q << (MQ - level);
+        const float2 w = tw[idx & (H - 1)];
+        const bool upper = (idx & H) != 0;
+        return make_float2(upper ? 0.0f - w.y : w.x, upper ? w.x : w.y);
+    }
+};
+
 // Stages S+1 .. S+RP of a group of 2^MA positions on the E registers of one
 // thread.  The group's position p is the transform's position lo_g + (p << A)
 // (A = 0, lo_g = 0 for a whole transform), so its local stage s is stage A + s
-// of eq. (6) and a local twiddle index ql becomes q = lo_g + (ql << A).  The
-// twiddle of table entry idx is read at tw[idx - TWOFF] (TWOFF > 0 when only
-// the upper part of the table is staged).
-template <int E, int LT, int S, int RP, int TWOFF = 0, int A = 0>
+// of eq. (6) and a local twiddle index ql becomes q = lo_g + (ql << A).  TW is
+// the twiddle source for the non-trivial rotations.
+template <int E, int LT, int S, int RP, class TW = TwTable<0>, int A = 0>
 __device__ __forceinline__ void stages(float (&vr)[E], float (&vi)[E], int t, const float2* __restrict__ tw,
                                        int lo_g = 0)
 {
@@ -84,7 +113,7 @@ __device__ __forceinline__ void stages(float (&vr)[E], float (&vi)[E], int t, co
             } else {
                 const int o = t + ((u >> RP) << LT);
                 const int ql = (o & ((1 << S) - 1)) + ((u & (half - 1)) << S);
-                const float2 w = tw[(1 << (A + S + k - 1)) - TWOFF + lo_g + (ql << A)];
+                const float2 w = TW::get(tw, A + S + k, lo_g + (ql << A));
                 rotate(ar, ai, w.x, w.y);
             }
             const float ur = vr[u], ui = vi[u];
@@ -228,7 +257,7 @@ __device__ __forceinline__ void later_passes_dif(float (&vr)[E], float (&vi)[E],
 // the pass's stages (A, lo_g as for stages()).  SYNC_T is the thread count
 // whose exchange ordering is needed (the group's own T when its threads are
 // consecutive lanes; anything above 64 forces workgroup barriers).
-template <int M, int RB, int P, bool SPLIT, int E, int TWOFF, int A = 0, int SYNC_T = (1 << (M - RB))>
+template <int M, int RB, int P, bool SPLIT, int E, class TW, int A = 0, int SYNC_T = (1 << (M - RB))>
 __device__ __forceinline__ void later_passes(float (&vr)[E], float (&vi)[E], float* lr, float* li, int t,
                                              const float2* __restrict__ tw, int lo_g = 0)
 {
@@ -253,8 +282,8 @@ __device__ __forceinline__ void later_passes(float (&vr)[E], float (&vi)[E], flo
             lds_get<E, LT, Cur::S, Cur::RP>(vi, li, t);
             xsync<SYNC_T>();
         }
-        stages<E, LT, Cur::S, Cur::RP, TWOFF, A>(vr, vi, t, tw, lo_g);
-        later_passes<M, RB, P + 1, SPLIT, E, TWOFF, A, SYNC_T>(vr, vi, lr, li, t, tw, lo_g);
+        stages<E, LT, Cur::S, Cur::RP, TW, A>(vr, vi, t, tw, lo_g);
+        later_passes<M, RB, P + 1, SPLIT, E, TW, A, SYNC_T>(vr, vi, lr, li, t, tw, lo_g);
     }
 }
 

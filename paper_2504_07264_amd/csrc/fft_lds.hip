@@ -36,10 +36,13 @@
 // bit, the factors of eq. (6) applied one after the other in FP32.
 #include "fft_device.h"
 
+#include <atomic>
 #include <climits>
 
 namespace splitdft {
 namespace {
+
+constexpr int kMaxDevices = 64;
 
 // Compile-time schedule of one kernel instance.
 //   M      log2 of the transform length
@@ -47,14 +50,22 @@ namespace {
 //   TPW    transforms per workgroup
 //   SPLIT  exchange one plane at a time through LDS (half the LDS)
 //   NT     nontemporal hints on the streaming global loads and stores
-//   TWL    twiddles of passes >= 1 staged once per workgroup in LDS
+//   TWL    twiddles of passes >= 1: 0 read from the table in global memory;
+//          staged once per workgroup in LDS: 1 table entries [2^RB, N),
+//          2 the first quarter turn of stage M (TwQuarter); 3 that quarter
+//          turn read from global memory
 //   WPE    minimum waves per SIMD the register allocation must allow (1 = any)
-//   F4IO   global loads and stores as 16-byte vectors over the workgroup's
-//          contiguous rows, staged through LDS in both directions
-template <int M_, int RB_, int TPW_, bool SPLIT_, bool NT_, bool TWL_, int WPE_, bool F4IO_ = false>
+//   F4IO   global I/O as 16-byte vectors over the workgroup's contiguous
+//          rows, staged through LDS: 0 none, 1 loads and stores, 2 loads only
+//   PF     persistent workgroups with a grid-stride loop over blocks of TPW
+//          transforms; the 16-byte loads of the next block are issued into
+//          registers before the current block's passes (needs F4IO != 0)
+template <int M_, int RB_, int TPW_, bool SPLIT_, bool NT_, int TWL_, int WPE_, int F4IO_ = 0, bool PF_ = false>
 struct Cfg {
-    static constexpr int M = M_, RB = RB_, TPW = TPW_, WPE = WPE_;
-    static constexpr bool SPLIT = SPLIT_, NT = NT_, TWL = TWL_, F4IO = F4IO_;
+    static constexpr int M = M_, RB = RB_, TPW = TPW_, WPE = WPE_, TWL = TWL_;
+    static constexpr bool SPLIT = SPLIT_, NT = NT_, PF = PF_;
+    static constexpr bool F4IN = F4IO_ != 0, F4OUT = F4IO_ == 1;
+    static constexpr int F4IO = F4IO_;
     static constexpr int N = 1 << M;
     static constexpr int E = 1 << RB;
     static constexpr int LT = M - RB;
@@ -64,12 +75,16 @@ struct Cfg {
     // LDS words per transform: the padded length, made odd when one wave
     // spans many transforms so that their slots start on different banks
     static constexpr int SLOT = T >= 32 ? lds_index(N) : (lds_index(N) | 1);
-    static constexpr bool USES_XCH = NP > 1 || F4IO;
+    static constexpr bool USES_XCH = NP > 1 || F4IN;
     static constexpr int XCH_WORDS = USES_XCH ? TPW * SLOT * (SPLIT ? 1 : 2) : 1;
     // twiddle entries [2^RB, N) are the ones passes >= 1 read
-    static constexpr int TW_LDS = (TWL && NP > 1) ? (N - E) : 0;
-    static constexpr int LDS_BYTES = 4 * XCH_WORDS + 8 * TW_LDS;
-    static_assert(!F4IO || E >= 4, "16-byte I/O needs at least 4 elements per thread");
+    static constexpr int TW_LDS = (TWL == 1 && NP > 1) ? (N - E) : 0;
+    // quarter-turn table of stage M
+    static constexpr int TWQ = (TWL == 2 && NP > 1) ? (N / 4) : 0;
+    static constexpr int LDS_BYTES = 4 * XCH_WORDS + 8 * TW_LDS + 8 * TWQ;
+    static_assert(!F4IN || E >= 4, "16-byte I/O needs at least 4 elements per thread");
+    static_assert(TWL < 2 || M >= 3, "the quarter-turn table needs N >= 8");
+    static_assert(!PF || F4IN, "the prefetching form loads through the 16-byte staging");
 };
 
 // 16-byte loads of one plane of a sync group's rows (valid floats only) into
@@ -89,6 +104,36 @@ __device__ __forceinline__ void stage_in(const float* x, float* area, int64_t ba
             d[1] = v[1];
             d[2] = v[2];
             d[3] = v[3];
+        }
+    }
+}
+
+// stage_in in two steps, so that the loads can be issued early: the valid
+// 16-byte vectors of one plane of a sync group's rows into registers ...
+template <class C, int GT>
+__device__ __forceinline__ void load_rows(v4f (&r)[C::E / 4], const float* x, int64_t base, int valid, int gtid)
+{
+#pragma unroll
+    for (int c = 0; c < C::E / 4; ++c) {
+        const int f = 4 * (gtid + c * GT);
+        if (f < valid)
+            r[c] = load4<C::NT>(x + base + f);
+    }
+}
+
+// ... and from the registers into the LDS slots (layout of stage_in).
+template <class C, int GT>
+__device__ __forceinline__ void put_rows(const v4f (&r)[C::E / 4], float* area, int valid, int gtid)
+{
+#pragma unroll
+    for (int c = 0; c < C::E / 4; ++c) {
+        const int f = 4 * (gtid + c * GT);
+        if (f < valid) {
+            float* d = area + (f >> C::M) * C::SLOT + lds_index(f & (C::N - 1));
+            d[0] = r[c][0];
+            d[1] = r[c][1];
+            d[2] = r[c][2];
+            d[3] = r[c][3];
         }
     }
 }
@@ -136,7 +181,7 @@ split_fft_lds_kernel(const float* xr, const float* xi, float* yr, float* yi, con
     constexpr int N = C::N, E = C::E, LT = C::LT, T = C::T, NP = C::NP;
     constexpr bool NT = C::NT;
     __shared__ float lds[C::XCH_WORDS];
-    __shared__ v4f lds_tw4[C::TW_LDS > 0 ? C::TW_LDS / 2 : 1];
+    __shared__ v4f lds_tw4[C::TW_LDS > 0 ? C::TW_LDS / 2 : (C::TWQ > 0 ? C::TWQ / 2 : 1)];
 
     const int tid = threadIdx.x;
     const int slot = tid >> LT;
@@ -161,10 +206,15 @@ split_fft_lds_kernel(const float* xr, const float* xi, float* yr, float* yi, con
         for (int k = tid; k < C::TW_LDS / 2; k += C::THREADS)
             lds_tw4[k] = src[k];
         __syncthreads();
+    } else if constexpr (C::TWQ > 0) {
+        const v4f* src = reinterpret_cast<const v4f*>(tw + N / 2);
+        for (int k = tid; k < C::TWQ / 2; k += C::THREADS)
+            lds_tw4[k] = src[k];
+        __syncthreads();
     }
 
     float vr[E], vi[E];
-    if constexpr (C::F4IO) {
+    if constexpr (C::F4IN) {
         const int64_t rows_left = batch - (b0 + gslot0);
         const int valid = static_cast<int>(rows_left < GSLOTS ? (rows_left > 0 ? rows_left : 0) : GSLOTS) * N;
         const int64_t base = (b0 + gslot0) * N;
@@ -228,12 +278,18 @@ split_fft_lds_kernel(const float* xr, const float* xi, float* yr, float* yi, con
 
     if constexpr (NP > 1) {
         if constexpr (C::TW_LDS > 0)
-            later_passes<M, RB, 1, C::SPLIT, E, E>(vr, vi, lr, li, t, reinterpret_cast<const float2*>(lds_tw4));
+            later_passes<M, RB, 1, C::SPLIT, E, TwTable<E>>(vr, vi, lr, li, t,
+                                                           reinterpret_cast<const float2*>(lds_tw4));
+        else if constexpr (C::TWQ > 0)
+            later_passes<M, RB, 1, C::SPLIT, E, TwQuarter<M>>(vr, vi, lr, li, t,
+                                                             reinterpret_cast<const float2*>(lds_tw4));
+        else if constexpr (C::TWL == 3)
+            later_passes<M, RB, 1, C::SPLIT, E, TwQuarter<M>>(vr, vi, lr, li, t, tw + N / 2);
         else
-            later_passes<M, RB, 1, C::SPLIT, E, 0>(vr, vi, lr, li, t, tw);
+            later_passes<M, RB, 1, C::SPLIT, E, TwTable<0>>(vr, vi, lr, li, t, tw);
     }
 
-    if constexpr (C::F4IO) {
+    if constexpr (C::F4OUT) {
         const int64_t rows_left = batch - (b0 + gslot0);
         const int valid = static_cast<int>(rows_left < GSLOTS ? (rows_left > 0 ? rows_left : 0) : GSLOTS) * N;
         const int64_t base = (b0 + gslot0) * N;
@@ -279,6 +335,161 @@ split_fft_lds_kernel(const float* xr, const float* xi, float* yr, float* yi, con
             const int64_t idx = row + position<LT, Last::S, Last::RP>(t, u);
             store1<NT>(yr + idx, vr[u]);
             store1<NT>(yi + idx, vi[u]);
+        }
+    }
+}
+
+// The values must exist in registers at this point of the program.
+template <int E>
+__device__ __forceinline__ void pin_regs(float (&v)[E])
+{
+#pragma unroll
+    for (int u = 0; u < E; ++u)
+        asm volatile("" : "+v"(v[u]));
+}
+
+// Persistent form of split_fft_lds_kernel (C::PF): the same arithmetic and
+// data movement per block of TPW transforms, but each workgroup loops over
+// blocks blockIdx.x, blockIdx.x + gridDim.x, ...  The twiddles are staged in
+// LDS once per workgroup, and the 16-byte loads of the next block go into
+// registers right after the current block has left them, so that they are
+// in flight during the current block's passes and stores.
+template <class C>
+__global__ void __launch_bounds__(C::THREADS) __attribute__((amdgpu_waves_per_eu(C::WPE)))
+split_fft_pf_kernel(const float* xr, const float* xi, float* yr, float* yi, const float2* __restrict__ tw,
+                    int64_t batch)
+{
+    constexpr int M = C::M, RB = C::RB, TPW = C::TPW;
+    constexpr int N = C::N, E = C::E, LT = C::LT, T = C::T, NP = C::NP;
+    constexpr bool NT = C::NT;
+    static_assert(C::PF && C::F4IN, "persistent form of the staged-load schedules");
+    __shared__ float lds[C::XCH_WORDS];
+    __shared__ v4f lds_tw4[C::TW_LDS > 0 ? C::TW_LDS / 2 : (C::TWQ > 0 ? C::TWQ / 2 : 1)];
+    const int tid = threadIdx.x;
+    const int slot = tid >> LT;
+    const int t0 = tid & (T - 1);
+    float* lr = lds + slot * C::SLOT;
+    float* li = C::SPLIT ? lr : lr + TPW * C::SLOT;
+    constexpr int GT = (T <= 64) ? (C::THREADS < 64 ? C::THREADS : 64) : C::THREADS;
+    constexpr int GSLOTS = GT / T;
+    const int gtid = tid & (GT - 1);
+    const int gslot0 = (tid / GT) * GSLOTS;
+    float* gr = lds + gslot0 * C::SLOT;
+    float* gi = C::SPLIT ? gr : gr + TPW * C::SLOT;
+
+    if constexpr (C::TW_LDS > 0) {
+        const v4f* src = reinterpret_cast<const v4f*>(tw + E);
+        for (int k = tid; k < C::TW_LDS / 2; k += C::THREADS)
+            lds_tw4[k] = src[k];
+        __syncthreads();
+    } else if constexpr (C::TWQ > 0) {
+        const v4f* src = reinterpret_cast<const v4f*>(tw + N / 2);
+        for (int k = tid; k < C::TWQ / 2; k += C::THREADS)
+            lds_tw4[k] = src[k];
+        __syncthreads();
+    }
+
+    const int64_t blocks = (batch + TPW - 1) / TPW;
+    // floats of the sync group's rows that exist in block blk
+    auto group_valid = [&](int64_t blk) {
+        const int64_t rows_left = batch - (blk * TPW + gslot0);
+        return static_cast<int>(rows_left < GSLOTS ? (rows_left > 0 ? rows_left : 0) : GSLOTS) * N;
+    };
+
+    v4f pr[E / 4], pi[E / 4];
+    int64_t blk = blockIdx.x;
+    if (blk < blocks) {
+        const int valid = group_valid(blk);
+        const int64_t base = (blk * TPW + gslot0) * N;
+        load_rows<C, GT>(pr, xr, base, valid, gtid);
+        load_rows<C, GT>(pi, xi, base, valid, gtid);
+    }
+    for (; blk < blocks; blk += gridDim.x) {
+        const int valid = group_valid(blk);
+        const int64_t base = (blk * TPW + gslot0) * N;
+        // the position and twiddle addresses below depend only on t; an
+        // opaque copy per iteration keeps the compiler from hoisting all of
+        // them out of the loop into registers that the prefetch needs
+        int t = t0;
+        asm volatile("" : "+v"(t));
+        float vr[E], vi[E];
+        if constexpr (C::SPLIT) {
+            put_rows<C, GT>(pr, gr, valid, gtid);
+            xsync<T>();
+            regs_from_natural<C>(vr, lr, t);
+            xsync<T>();
+            put_rows<C, GT>(pi, gr, valid, gtid);
+            xsync<T>();
+            regs_from_natural<C>(vi, lr, t);
+        } else {
+            put_rows<C, GT>(pr, gr, valid, gtid);
+            put_rows<C, GT>(pi, gi, valid, gtid);
+            xsync<T>();
+            regs_from_natural<C>(vr, lr, t);
+            regs_from_natural<C>(vi, li, t);
+        }
+        // The LDS reads above must complete before the barrier: the compiler
+        // has been seen to sink them past it into the block after the
+        // prefetch branch, where faster waves already overwrite the slots.
+        // Taking the values through an opaque definition here pins them.
+        pin_regs<E>(vr);
+        pin_regs<E>(vi);
+        xsync<T>();
+
+        // the next block's loads, in flight during this block's work
+        const int64_t nblk = blk + gridDim.x;
+        if (nblk < blocks) {
+            const int nvalid = group_valid(nblk);
+            const int64_t nbase = (nblk * TPW + gslot0) * N;
+            load_rows<C, GT>(pr, xr, nbase, nvalid, gtid);
+            load_rows<C, GT>(pi, xi, nbase, nvalid, gtid);
+        }
+
+        stages<E, LT, 0, Pass<M, RB, 0>::RP>(vr, vi, t, tw);
+        if constexpr (NP > 1) {
+            if constexpr (C::TW_LDS > 0)
+                later_passes<M, RB, 1, C::SPLIT, E, TwTable<E>>(vr, vi, lr, li, t,
+                                                               reinterpret_cast<const float2*>(lds_tw4));
+            else if constexpr (C::TWQ > 0)
+                later_passes<M, RB, 1, C::SPLIT, E, TwQuarter<M>>(vr, vi, lr, li, t,
+                                                                 reinterpret_cast<const float2*>(lds_tw4));
+            else if constexpr (C::TWL == 3)
+                later_passes<M, RB, 1, C::SPLIT, E, TwQuarter<M>>(vr, vi, lr, li, t, tw + N / 2);
+            else
+                later_passes<M, RB, 1, C::SPLIT, E, TwTable<0>>(vr, vi, lr, li, t, tw);
+        }
+
+        if constexpr (C::F4OUT) {
+            if constexpr (C::SPLIT) {
+                regs_to_natural<C>(vr, lr, t);
+                xsync<T>();
+                stage_out<C, GT>(yr, gr, base, valid, gtid);
+                xsync<T>();
+                regs_to_natural<C>(vi, lr, t);
+                xsync<T>();
+                stage_out<C, GT>(yi, gr, base, valid, gtid);
+            } else {
+                regs_to_natural<C>(vr, lr, t);
+                regs_to_natural<C>(vi, li, t);
+                xsync<T>();
+                stage_out<C, GT>(yr, gr, base, valid, gtid);
+                stage_out<C, GT>(yi, gi, base, valid, gtid);
+            }
+            // the next block's put_rows reuses the slots
+            xsync<T>();
+        } else {
+            // the last exchange ended with a sync, so the slots are free
+            const int64_t b = blk * TPW + slot;
+            if (b < batch) {
+                using Last = Pass<M, RB, NP - 1>;
+                const int64_t row = b * N;
+#pragma unroll
+                for (int u = 0; u < E; ++u) {
+                    const int64_t idx = row + position<LT, Last::S, Last::RP>(t, u);
+                    store1<NT>(yr + idx, vr[u]);
+                    store1<NT>(yi + idx, vi[u]);
+                }
+            }
         }
     }
 }
@@ -413,20 +624,56 @@ hipError_t launch_lds(const float* xr, const float* xi, float* yr, float* yi, co
     return hipGetLastError();
 }
 
+// Workgroups of the persistent form: as many as can be resident at once.
+template <class C>
+hipError_t launch_pf(const float* xr, const float* xi, float* yr, float* yi, const float2* tw, int64_t batch,
+                     hipStream_t stream)
+{
+    const int64_t blocks = (batch + C::TPW - 1) / C::TPW;
+    // resident workgroups per device, looked up once (launches are frequent)
+    static std::atomic<int> resident_of[kMaxDevices];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    int resident = (dev >= 0 && dev < kMaxDevices) ? resident_of[dev].load(std::memory_order_relaxed) : 0;
+    if (resident <= 0) {
+        int cus = 0, per_cu = 0;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, split_fft_pf_kernel<C>, C::THREADS, 0);
+        if (e != hipSuccess)
+            return e;
+        if (per_cu < 1 || cus < 1)
+            return hipErrorInvalidConfiguration;
+        resident = cus * per_cu;
+        if (dev >= 0 && dev < kMaxDevices)
+            resident_of[dev].store(resident, std::memory_order_relaxed);
+    }
+    const int64_t grid = blocks < resident ? blocks : resident;
+    hipLaunchKernelGGL(split_fft_pf_kernel<C>, dim3(static_cast<unsigned>(grid)), dim3(C::THREADS), 0, stream, xr,
+                       xi, yr, yi, tw, batch);
+    return hipGetLastError();
+}
+
 template <class C>
 constexpr Variant make_variant()
 {
-    return Variant{C::M,  C::RB,  C::TPW, C::THREADS, C::LDS_BYTES, C::SPLIT,
-                   C::NT, C::TWL, C::WPE, C::F4IO,    &launch_lds<C>};
+    if constexpr (C::PF)
+        return Variant{C::M,   C::RB,  C::TPW,  C::THREADS, C::LDS_BYTES, C::SPLIT,
+                       C::NT,  C::TWL, C::WPE,  C::F4IO,    &launch_pf<C>, true};
+    else
+        return Variant{C::M,   C::RB,  C::TPW,  C::THREADS, C::LDS_BYTES, C::SPLIT,
+                       C::NT,  C::TWL, C::WPE,  C::F4IO,    &launch_lds<C>, false};
 }
 
 // Compiled schedules per length; the first entry of each list is the default.
 //                              M   RB  TPW  SPLIT  NT     TWL    WPE
 const Variant kV0[] = {Variant{0, 0, 256, 256, 0, false, false, false, 1, false, &launch_len1}};
-template <int M, int RB, int TPW, bool SPLIT, bool NT, bool TWL, int WPE, bool F4IO = false>
+template <int M, int RB, int TPW, bool SPLIT, bool NT, int TWL, int WPE, int F4IO = 0, bool PF = false>
 constexpr Variant V()
 {
-    return make_variant<Cfg<M, RB, TPW, SPLIT, NT, TWL, WPE, F4IO>>();
+    return make_variant<Cfg<M, RB, TPW, SPLIT, NT, TWL, WPE, F4IO, PF>>();
 }
 
 constexpr bool Y = true, _ = false;
@@ -434,23 +681,28 @@ constexpr bool Y = true, _ = false;
 const Variant kV1[] = {V<1, 1, 256, _, _, _, 1>()};
 const Variant kV2[] = {V<2, 2, 256, _, _, _, 1>()};
 const Variant kV3[] = {V<3, 3, 256, _, _, _, 1>()};
-const Variant kV4[] = {V<4, 4, 64, _, Y, _, 1, Y>(), V<4, 4, 64, _, _, _, 1, Y>(), V<4, 4, 64, _, _, _, 1>(),
-                       V<4, 4, 256, _, _, _, 1, Y>()};
-const Variant kV5[] = {V<5, 4, 64, _, Y, Y, 1, Y>(), V<5, 4, 64, _, _, Y, 1, Y>(), V<5, 5, 128, _, _, _, 1>()};
-const Variant kV6[] = {V<6, 4, 64, _, Y, Y, 1, Y>(), V<6, 4, 32, _, _, Y, 1, Y>(), V<6, 3, 32, _, _, _, 1>()};
-const Variant kV7[] = {V<7, 4, 16, _, Y, Y, 1, Y>(), V<7, 4, 16, _, _, Y, 1, Y>(), V<7, 4, 32, _, _, _, 1>()};
-const Variant kV8[] = {V<8, 4, 16, Y, Y, Y, 4, Y>(), V<8, 4, 16, _, Y, Y, 1, Y>(), V<8, 4, 16, _, _, _, 1>(),
-                       V<8, 4, 32, Y, Y, Y, 4, Y>()};
-const Variant kV9[] = {V<9, 4, 8, Y, Y, Y, 4, Y>(), V<9, 4, 8, _, Y, Y, 1>(), V<9, 4, 8, _, Y, Y, 1, Y>(),
-                       V<9, 4, 16, Y, Y, Y, 4, Y>()};
-const Variant kV10[] = {V<10, 4, 8, Y, Y, Y, 4>(),    V<10, 4, 4, Y, Y, Y, 4>(),    V<10, 4, 4, Y, Y, Y, 4, Y>(),
-                        V<10, 5, 8, Y, Y, Y, 1>(),    V<10, 4, 8, Y, Y, Y, 4, Y>(), V<10, 4, 16, Y, Y, Y, 4>()};
-const Variant kV11[] = {V<11, 5, 4, Y, Y, Y, 1>(), V<11, 4, 2, Y, Y, Y, 4, Y>(), V<11, 5, 4, Y, Y, Y, 1, Y>()};
-const Variant kV12[] = {V<12, 5, 2, Y, Y, Y, 2>(), V<12, 5, 2, _, Y, _, 1>(), V<12, 5, 2, Y, Y, Y, 1>(),
-                        V<12, 4, 2, Y, Y, Y, 4>(), V<12, 4, 1, Y, Y, Y, 4, Y>()};
-const Variant kV13[] = {V<13, 5, 1, _, Y, _, 1>(), V<13, 5, 1, Y, Y, _, 1, Y>()};
-const Variant kV14[] = {V<14, 5, 1, _, Y, _, 1>(), V<14, 5, 1, Y, Y, _, 1>()};
-const Variant kV15[] = {V<15, 5, 1, Y, Y, _, 1>()};
+const Variant kV4[] = {V<4, 4, 64, _, Y, _, 4, 1, Y>(), V<4, 4, 64, _, Y, _, 1, Y>(), V<4, 4, 256, _, Y, _, 4, 1, Y>(),
+                       V<4, 4, 64, _, _, _, 1>()};
+const Variant kV5[] = {V<5, 4, 64, _, Y, 2, 4, 1, Y>(), V<5, 4, 64, _, Y, Y, 1, Y>(), V<5, 5, 128, _, _, _, 1>()};
+const Variant kV6[] = {V<6, 4, 64, _, Y, 2, 4, 1, Y>(), V<6, 4, 32, _, Y, 2, 4, 1, Y>(), V<6, 4, 64, _, Y, Y, 1, Y>(),
+                       V<6, 3, 32, _, _, _, 1>()};
+const Variant kV7[] = {V<7, 4, 32, Y, Y, 2, 4, 1, Y>(), V<7, 4, 16, _, Y, 2, 4, 1, Y>(), V<7, 4, 16, _, Y, Y, 1, Y>(),
+                       V<7, 4, 32, _, _, _, 1>()};
+const Variant kV8[] = {V<8, 4, 16, Y, Y, 2, 4, 1, Y>(), V<8, 4, 16, Y, Y, Y, 4, Y>(), V<8, 4, 32, Y, Y, 2, 4, 1, Y>(),
+                       V<8, 4, 16, _, _, _, 1>()};
+const Variant kV9[] = {V<9, 4, 8, Y, Y, 2, 4, 2, Y>(), V<9, 4, 8, Y, Y, 2, 4, 1, Y>(), V<9, 4, 4, Y, Y, 2, 4, 2, Y>(),
+                       V<9, 4, 8, Y, Y, Y, 4, Y>(),    V<9, 4, 8, _, Y, Y, 1>()};
+const Variant kV10[] = {V<10, 4, 4, _, Y, 2, 4, 2, Y>(), V<10, 4, 4, Y, Y, 2, 4, 2, Y>(), V<10, 4, 4, Y, Y, 1, 4, 2, Y>(),
+                        V<10, 4, 4, Y, Y, 2, 3, 2, Y>(), V<10, 4, 8, Y, Y, 2, 3, 2, Y>(), V<10, 4, 2, Y, Y, 2, 4, 2, Y>(),
+                        V<10, 4, 8, Y, Y, 2, 4, 2, Y>(), V<10, 4, 8, Y, Y, Y, 4>(),       V<10, 5, 8, Y, Y, Y, 1>()};
+const Variant kV11[] = {V<11, 4, 1, Y, Y, 2, 4, 2, Y>(), V<11, 4, 2, Y, Y, 2, 4, 2, Y>(), V<11, 4, 1, _, Y, 2, 4, 2, Y>(),
+                        V<11, 4, 2, Y, Y, 2, 4>(),       V<11, 5, 4, Y, Y, Y, 1>()};
+const Variant kV12[] = {V<12, 4, 1, Y, Y, 2, 4, 2>(),    V<12, 5, 2, Y, Y, 2, 2>(),    V<12, 4, 1, Y, Y, 2, 3, 2, Y>(),
+                        V<12, 5, 2, Y, Y, Y, 2>(),       V<12, 4, 1, _, Y, 2, 4, 2>()};
+const Variant kV13[] = {V<13, 4, 1, Y, Y, 2, 4, 2, Y>(), V<13, 4, 1, Y, Y, 2, 1, 2>(), V<13, 5, 1, _, Y, _, 1>()};
+const Variant kV14[] = {V<14, 4, 1, Y, Y, 2, 1, 2, Y>(), V<14, 4, 1, Y, Y, 3, 1, 2, Y>(), V<14, 5, 1, Y, Y, 2, 2, 2, Y>(),
+                        V<14, 4, 1, Y, Y, 2, 1, 2>()};
+const Variant kV15[] = {V<15, 5, 1, Y, Y, 3, 1, 2>(), V<15, 5, 1, Y, Y, _, 1>()};
 
 struct VariantList {
     const Variant* v;

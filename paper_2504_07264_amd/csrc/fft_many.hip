@@ -134,7 +134,7 @@ __device__ __noinline__ void many_group(Planes pl, const int64_t* __restrict__ o
 
     stages<E, LT, 0, Pass<M, RB, 0>::RP>(vr, vi, t, tw);
     if constexpr (G::NP > 1)
-        later_passes<M, RB, 1, true, E, 0>(vr, vi, lr, lr, t, tw);
+        later_passes<M, RB, 1, true, E, TwTable<0>>(vr, vi, lr, lr, t, tw);
 
     using Last = Pass<M, RB, G::NP - 1>;
 #pragma unroll

@@ -144,9 +144,9 @@ __device__ __forceinline__ void tile_process(const float* xr, const float* xi, f
     __syncthreads();
 
     const int lo_g = TC::PASS == 1 ? 0 : col0 + g;
-    stages<E, LT, 0, Pass<TC::MA, TC::RB, 0>::RP, 0, TC::TW_SHIFT>(vr, vi, t, tw, lo_g);
+    stages<E, LT, 0, Pass<TC::MA, TC::RB, 0>::RP, TwTable<0>, TC::TW_SHIFT>(vr, vi, t, tw, lo_g);
     if constexpr (TC::NP > 1)
-        later_passes<TC::MA, TC::RB, 1, TC::SPLIT, E, 0, TC::TW_SHIFT, TC::GF ? 1024 : T>(vr, vi, lr, li, t, tw,
+        later_passes<TC::MA, TC::RB, 1, TC::SPLIT, E, TwTable<0>, TC::TW_SHIFT, TC::GF ? 1024 : T>(vr, vi, lr, li, t, tw,
                                                                                        lo_g);
 
     // the group's slot is free again (its last exchange ended with a sync)

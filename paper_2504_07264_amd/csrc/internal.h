@@ -21,11 +21,12 @@ struct Variant {
     int lds_bytes;
     bool split;   // LDS exchange one plane at a time
     bool nt;      // nontemporal streaming loads/stores
-    bool twl;     // twiddles of passes >= 1 staged in LDS
+    int twl;      // twiddles of passes >= 1 in LDS: 0 no, 1 table slice, 2 quarter turn
     int wpe;      // occupancy hint (minimum waves per SIMD)
-    bool f4io;    // 16-byte global I/O staged through LDS
+    int f4io;     // 16-byte global I/O staged through LDS: 0 no, 1 both ways, 2 loads
     hipError_t (*launch)(const float* xr, const float* xi, float* yr, float* yi,
                          const float2* tw, int64_t batch, hipStream_t stream);
+    bool pf = false;  // persistent workgroups, next block's loads prefetched
 };
 
 // A two-pass schedule for large lengths: pass 1 runs stages 1..a on blocks of

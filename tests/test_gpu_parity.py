@@ -96,6 +96,30 @@ def test_every_length_and_schedule(m):
         assert_within_tol(yr, yi, rr, ri, n)
 
 
+@pytest.mark.parametrize("m", range(10, 15))
+def test_persistent_schedules_many_blocks_per_workgroup(m):
+    # The persistent schedules loop over blocks with a grid stride and
+    # prefetch the next block: a batch of about 2^24 points gives every
+    # resident workgroup several blocks, and an odd batch a ragged last block.
+    n = 1 << m
+    batch = ((1 << 24) // n + 3) | 1
+    flags_list = []
+    for flags in all_variants(m)[1:]:
+        with Plan(n, 1, flags) as p:
+            if "persistent" in p.describe():
+                flags_list.append(flags)
+    if not flags_list:
+        pytest.skip("no persistent schedule for n = %d" % n)
+    xr, xi = inputs.draw_planes(n, batch, "normal", 3000 + m)
+    mr, mi = oracle.split_fft_f32(xr.numpy(), xi.numpy())
+    for flags in flags_list:
+        yr, yi = gpu_exec(n, batch, xr, xi, flags)
+        assert_bit_exact(yr, yi, mr, mi)
+        yr, yi = gpu_exec(n, batch, xr, xi, flags, adjoint=True)
+        ar, ai = oracle.split_adjoint_f32(xr.numpy(), xi.numpy())
+        assert_bit_exact(yr, yi, ar, ai)
+
+
 @pytest.mark.parametrize("m", [0, 1, 4, 7, 10, 12, 15, 16])
 def test_adjoint_every_length(m):
     n = 1 << m
