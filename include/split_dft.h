@@ -133,7 +133,7 @@ split_dft_status split_dft_adjoint_ws(split_dft_plan_t plan, const float *gr, co
 split_dft_status split_dft_destroy(split_dft_plan_t plan);
 
 /* Workspace bytes a plan needs beyond inputs and outputs: 0 for lengths
- * handled in a single pass; for two-pass plans (n = 2^16 by default) the
+ * handled in a single pass; for two-pass plans (n >= 2^15 by default) the
  * intermediate of one chunk of transforms, both planes (at most 128 MiB or one
  * transform).  0 for a NULL or destroyed plan. */
 size_t split_dft_workspace_bytes(split_dft_plan_t plan);
@@ -161,23 +161,32 @@ split_dft_status split_dft_twiddle_table(int m, float *c, float *s);
  * back to back in each plane: transform k occupies [offset_k, offset_k + N_k)
  * with offset_0 = 0 and offset_(k+1) = offset_k + N_k (split_dft_many_offsets).
  * Each transform is the operation of split_dft_exec (eq. (6) applied in order,
- * bit-identical to it), and the adjoint that of split_dft_adjoint.  One call
- * is one persistent kernel launch: workgroups take work items (a group of
- * short transforms of one length, or one transform of length >= 2^14 run
- * through a per-workgroup workspace) from a device counter, largest first.
- * The counter returns to zero at the end of every launch, so launches can be
- * replayed from a graph; launches of one grouped plan must not overlap in
- * time (use one stream).  Pointer rules as for split_dft_exec (16-byte
- * aligned, outputs may coincide exactly with their own direction's inputs).
- */
+ * bit-identical to it), and the adjoint that of split_dft_adjoint.
+ *
+ * Lengths up to 2^13 run in one persistent kernel launch: workgroups take
+ * work items (a group of short transforms of one length) from a device
+ * counter, largest first.  By default each length from 2^14 up runs in its
+ * own launches of the single-length kernels, addressed through the
+ * transforms' offsets (two passes through the plan's workspace from 2^15), all
+ * on the caller's stream before the persistent launch; with
+ * SPLIT_DFT_MANY_ONE_KERNEL every length runs in the persistent kernel (one
+ * transform of length >= 2^14 per work item, through a per-workgroup
+ * workspace).  The counter returns to zero at the end of every launch, so
+ * calls can be replayed from a graph; calls on one grouped plan must not
+ * overlap in time (use one stream).  Pointer rules as for split_dft_exec
+ * (16-byte aligned, outputs may coincide exactly with their own direction's
+ * inputs). */
 typedef struct split_dft_many_s *split_dft_many_t;
 typedef struct split_dft_graph_s *split_dft_graph_t;
 
 /* flags: bits 0-7 precision (SPLIT_DFT_FP32 only); bits 8-15 kernel build
  * (0 = default, k = build k-1: 0 two workgroups per CU, 1 one); bits 16-23
- * workgroups per CU (0 = as many as fit).  Allocates the device-side item
- * list, offsets, twiddle table and, when some length is >= 2^14, a workspace
- * of 512 KiB per persistent workgroup. */
+ * workgroups per CU (0 = as many as fit); SPLIT_DFT_MANY_ONE_KERNEL.
+ * Allocates the device-side item list, offsets and twiddle table, and a
+ * workspace: with SPLIT_DFT_MANY_ONE_KERNEL and some length >= 2^14, 512 KiB
+ * per persistent workgroup; by default, when some length is 2^15 or more, one
+ * two-pass chunk (at most 128 MiB). */
+#define SPLIT_DFT_MANY_ONE_KERNEL (1u << 24)
 split_dft_status split_dft_many_plan(split_dft_many_t *out, const int64_t *lengths, int64_t count,
                                      uint32_t flags);
 /* offsets: count + 1 entries (the last is the total number of points). */

@@ -33,10 +33,12 @@ namespace {
 
 thread_local std::string g_last_error;
 
-// Length 2^16 uses the two-pass schedule by default: one transform (512 KiB)
-// does not fit a CU's LDS and registers.  Lengths up to 2^15 run in a single
-// pass (measured faster than two passes, which move the data twice).
-constexpr int kTwoPassDefaultLog2N = 16;
+// Lengths 2^15 and 2^16 use the two-pass schedule by default.  A transform of
+// 2^16 (512 KiB) does not fit a CU's LDS and registers; one of 2^15 does, but
+// the single-workgroup kernel (one transform per CU) is bound by its
+// arithmetic and latency rather than by memory, and measured slower than two
+// passes on most devices.  Lengths up to 2^14 run in a single pass.
+constexpr int kTwoPassDefaultLog2N = 15;
 // Workspace per two-pass chunk (both planes); measured on MI355X, chunks of
 // 128 MiB beat smaller ones (fewer, larger launches).
 constexpr int64_t kTwoPassChunkBytes = int64_t{128} << 20;
@@ -149,9 +151,9 @@ split_dft_status run(split_dft_plan_t p, const float* xr, const float* xi, float
         for (int64_t s0 = 0; s0 < p->batch; s0 += p->chunk) {
             const int64_t k = p->batch - s0 < p->chunk ? p->batch - s0 : p->chunk;
             const int64_t off = s0 * p->n;
-            hipError_t e = p->two->pass1(xr + off, xi + off, wr, wi, p->d_tw, k, st);
+            hipError_t e = p->two->pass1(xr + off, xi + off, wr, wi, p->d_tw, k, nullptr, st);
             if (e == hipSuccess)
-                e = p->two->pass2(wr, wi, yr + off, yi + off, p->d_tw, k, st);
+                e = p->two->pass2(wr, wi, yr + off, yi + off, p->d_tw, k, nullptr, st);
             if (e != hipSuccess)
                 return fail_hip(e, "two-pass kernel launch");
         }
@@ -159,7 +161,7 @@ split_dft_status run(split_dft_plan_t p, const float* xr, const float* xi, float
     }
     const hipError_t e =
         p->mode == splitdft::kModeFP32
-            ? p->variant->launch(xr, xi, yr, yi, p->d_tw, p->batch, st)
+            ? p->variant->launch(xr, xi, yr, yi, p->d_tw, p->batch, nullptr, st)
             : splitdft::launch_mfma(p->mode, p->m, xr, xi, yr, yi, p->d_mfma,
                                     reinterpret_cast<const float2*>(p->d_mfma + splitdft::kMfmaConstFloats),
                                     p->batch, st);
@@ -269,6 +271,9 @@ split_dft_status split_dft_plan(split_dft_plan_t* out, int64_t n, int64_t batch,
                 chunk_bytes = std::atoll(cb) << 20;
         chunk = chunk_bytes / (n * 2 * static_cast<int64_t>(sizeof(float)));
         chunk = chunk < 1 ? 1 : (chunk > batch ? batch : chunk);
+        // equal chunks: no short launch at the end
+        const int64_t nchunks = (batch + chunk - 1) / chunk;
+        chunk = (batch + nchunks - 1) / nchunks;
         ws_bytes = static_cast<size_t>(chunk) * static_cast<size_t>(n) * 2 * sizeof(float);
         e = hipMalloc(&d_ws, ws_bytes);
         if (e != hipSuccess) {

@@ -15,10 +15,23 @@
 #include <unordered_set>
 #include <vector>
 
+// Transforms of one length >= 2^14 in the default (hybrid) mode: run by the
+// per-length kernels, addressed through their element offsets.
+struct ManyLarge {
+    int m;
+    int64_t count;
+    int64_t* d_rows;                     // element offsets, count entries
+    const splitdft::Variant* variant;    // single-pass schedule, or
+    const splitdft::TwoPass* two;        // two-pass schedule through d_ws
+    int64_t chunk;                       // transforms per workspace chunk
+};
+
 struct split_dft_many_s {
     int64_t count;
     int64_t points;
     int device;
+    bool one_kernel;  // every length in the grouped kernel
+    std::vector<ManyLarge> large;
     int variant;  // grouped-kernel build
     int grid;     // persistent workgroups
     std::vector<int64_t> offsets;  // host copy, count + 1 entries
@@ -71,6 +84,9 @@ bool ranges_overlap(const void* a, size_t abytes, const void* b, size_t bbytes)
 
 void free_many(split_dft_many_s* p)
 {
+    for (ManyLarge& g : p->large)
+        if (g.d_rows)
+            (void)hipFree(g.d_rows);
     for (void* q : {static_cast<void*>(p->d_offsets), static_cast<void*>(p->d_order),
                     static_cast<void*>(p->d_items_one), static_cast<void*>(p->d_items_both),
                     static_cast<void*>(p->d_queue), static_cast<void*>(p->d_ws), static_cast<void*>(p->d_tw)})
@@ -161,6 +177,31 @@ split_dft_status many_launch(split_dft_many_t p, const float* xr, const float* x
         a.in_r[d] = gi, a.in_i[d] = gr, a.out_r[d] = gxi, a.out_i[d] = gxr;
         ++d;
     }
+    // lengths >= 2^14 (default mode): per-length kernels, one direction at a time
+    for (const ManyLarge& g : p->large) {
+        for (int k = 0; k < d; ++k) {
+            hipError_t e = hipSuccess;
+            if (g.variant) {
+                e = g.variant->launch(a.in_r[k], a.in_i[k], a.out_r[k], a.out_i[k], p->d_tw, g.count, g.d_rows,
+                                      stream);
+            } else {
+                float* wr = p->d_ws;
+                float* wi = p->d_ws + g.chunk * (int64_t{1} << g.m);
+                for (int64_t s0 = 0; s0 < g.count && e == hipSuccess; s0 += g.chunk) {
+                    const int64_t c = g.count - s0 < g.chunk ? g.count - s0 : g.chunk;
+                    e = g.two->pass1(a.in_r[k], a.in_i[k], wr, wi, p->d_tw, c, g.d_rows + s0, stream);
+                    if (e == hipSuccess)
+                        e = g.two->pass2(wr, wi, a.out_r[k], a.out_i[k], p->d_tw, c, g.d_rows + s0, stream);
+                }
+            }
+            if (e != hipSuccess) {
+                *msg = std::string("per-length kernel launch: ") + hipGetErrorString(e);
+                return SPLIT_DFT_ERR_HIP;
+            }
+        }
+    }
+    if ((d == 2 ? p->n_both : p->n_one) == 0)
+        return SPLIT_DFT_OK;
     a.offsets = p->d_offsets;
     a.order = p->d_order;
     a.items = d == 2 ? p->d_items_both : p->d_items_one;
@@ -193,8 +234,9 @@ split_dft_status split_dft_many_plan(split_dft_many_t* out, const int64_t* lengt
         return fail(SPLIT_DFT_ERR_NULL_POINTER, "out or lengths is NULL");
     if (count < 1 || count > INT32_MAX)
         return fail(SPLIT_DFT_ERR_INVALID_BATCH, "count must be in [1, 2^31 - 1]");
-    if ((flags & 0xffu) != SPLIT_DFT_FP32 || (flags >> 24) != 0)
+    if ((flags & 0xffu) != SPLIT_DFT_FP32 || (flags >> 25) != 0)
         return fail(SPLIT_DFT_ERR_UNSUPPORTED, "unsupported flags " + std::to_string(flags));
+    const bool one_kernel = (flags & SPLIT_DFT_MANY_ONE_KERNEL) != 0;
     const int variant_sel = static_cast<int>((flags >> 8) & 0xffu);  // 0 = default build, k = build k-1
     const int wg_per_cu = static_cast<int>((flags >> 16) & 0xffu);   // 0 = as many as fit
     if (variant_sel > kManyKernelVariants)
@@ -212,7 +254,7 @@ split_dft_status split_dft_many_plan(split_dft_many_t* out, const int64_t* lengt
             return fail(SPLIT_DFT_ERR_INVALID_LENGTH,
                         "length " + std::to_string(k) + " = " + std::to_string(n) + " is not 2^m, 2 <= m <= 16");
         logs[static_cast<size_t>(k)] = m;
-        any_large = any_large || m > 13;
+        any_large = any_large || (m > 13 && one_kernel);
         if (offs[static_cast<size_t>(k)] > INT64_MAX / 8 - n)
             return fail(SPLIT_DFT_ERR_INVALID_BATCH, "total length overflows");
         offs[static_cast<size_t>(k) + 1] = offs[static_cast<size_t>(k)] + n;
@@ -225,11 +267,24 @@ split_dft_status split_dft_many_plan(split_dft_many_t* out, const int64_t* lengt
     std::stable_sort(order.begin(), order.end(),
                      [&](int32_t a, int32_t b) { return logs[static_cast<size_t>(a)] > logs[static_cast<size_t>(b)]; });
     std::vector<ManyItem> one, both;
+    struct LargeHost {
+        int m;
+        std::vector<int64_t> rows;
+    };
+    std::vector<LargeHost> large_host;
     for (size_t i = 0; i < order.size();) {
         const int m = logs[static_cast<size_t>(order[i])];
         size_t j = i;
         while (j < order.size() && logs[static_cast<size_t>(order[j])] == m)
             ++j;
+        if (!one_kernel && m >= kManyPerLengthLog2N) {
+            LargeHost g{m, {}};
+            for (size_t s = i; s < j; ++s)
+                g.rows.push_back(offs[static_cast<size_t>(order[s])]);
+            large_host.push_back(std::move(g));
+            i = j;
+            continue;
+        }
         const size_t per = static_cast<size_t>(many_items_per_group(m));
         for (size_t s = i; s < j; s += per) {
             const int cnt = static_cast<int>(std::min(per, j - s));
@@ -253,6 +308,7 @@ split_dft_status split_dft_many_plan(split_dft_many_t* out, const int64_t* lengt
     p->count = count;
     p->points = offs.back();
     p->offsets = offs;
+    p->one_kernel = one_kernel;
     p->variant = variant_sel == 0 ? 0 : variant_sel - 1;
     hipError_t e = hipGetDevice(&p->device);
     int cus = 0, per_cu = 0;
@@ -290,6 +346,35 @@ split_dft_status split_dft_many_plan(split_dft_many_t* out, const int64_t* lengt
         e = upload(&p->d_tw, tw);
     if (e == hipSuccess && any_large) {
         p->ws_bytes = static_cast<size_t>(p->grid) * 2 * static_cast<size_t>(kManyMaxN) * sizeof(float);
+        e = hipMalloc(&p->d_ws, p->ws_bytes);
+    }
+    // per-length kernels: schedules, offsets and the two-pass workspace
+    size_t ws2 = 0;
+    for (LargeHost& h : large_host) {
+        if (e != hipSuccess)
+            break;
+        ManyLarge g{h.m, static_cast<int64_t>(h.rows.size()), nullptr, nullptr, nullptr, 0};
+        const Variant* v = default_variant(h.m, g.count);
+        int c2 = 0;
+        const TwoPass* two = two_pass_for(h.m, &c2);
+        if (h.m < kManyTwoPassLog2N && v && v->rows_ok) {
+            g.variant = v;
+        } else if (two && c2 > 0) {
+            g.two = &two[0];
+            const int64_t n = int64_t{1} << h.m;
+            g.chunk = std::max<int64_t>(1, std::min<int64_t>(g.count, kManyChunkBytes / (n * 2 * 4)));
+            const int64_t nchunks = (g.count + g.chunk - 1) / g.chunk;
+            g.chunk = (g.count + nchunks - 1) / nchunks;  // equal chunks
+            ws2 = std::max(ws2, static_cast<size_t>(g.chunk) * static_cast<size_t>(n) * 2 * sizeof(float));
+        } else {
+            e = hipErrorInvalidConfiguration;
+            break;
+        }
+        e = upload(&g.d_rows, h.rows);
+        p->large.push_back(g);
+    }
+    if (e == hipSuccess && ws2 > 0) {
+        p->ws_bytes = ws2;
         e = hipMalloc(&p->d_ws, p->ws_bytes);
     }
     if (e != hipSuccess) {

@@ -175,7 +175,7 @@ __device__ __forceinline__ void regs_to_natural(const float (&v)[C::E], float* s
 template <class C>
 __global__ void __launch_bounds__(C::THREADS) __attribute__((amdgpu_waves_per_eu(C::WPE)))
 split_fft_lds_kernel(const float* xr, const float* xi, float* yr, float* yi, const float2* __restrict__ tw,
-                     int64_t batch)
+                     int64_t batch, const int64_t* __restrict__ rows)
 {
     constexpr int M = C::M, RB = C::RB, TPW = C::TPW;
     constexpr int N = C::N, E = C::E, LT = C::LT, T = C::T, NP = C::NP;
@@ -189,7 +189,9 @@ split_fft_lds_kernel(const float* xr, const float* xi, float* yr, float* yi, con
     const int64_t b0 = static_cast<int64_t>(blockIdx.x) * TPW;
     const int64_t b = b0 + slot;
     const bool active = b < batch;
-    const int64_t row = b * N;
+    // rows (one transform per workgroup only): element offset of each transform
+    const bool indirect = TPW == 1 && rows != nullptr;
+    const int64_t row = indirect ? (active ? rows[b] : 0) : b * N;
     float* lr = lds + slot * C::SLOT;
     float* li = C::SPLIT ? lr : lr + TPW * C::SLOT;
     // sync group of the LDS exchanges: one wave when a transform fits in it
@@ -217,14 +219,18 @@ split_fft_lds_kernel(const float* xr, const float* xi, float* yr, float* yi, con
     if constexpr (C::F4IN) {
         const int64_t rows_left = batch - (b0 + gslot0);
         const int valid = static_cast<int>(rows_left < GSLOTS ? (rows_left > 0 ? rows_left : 0) : GSLOTS) * N;
-        const int64_t base = (b0 + gslot0) * N;
+        const int64_t base = indirect ? row : (b0 + gslot0) * N;
         float* gr = lds + gslot0 * C::SLOT;
         if constexpr (C::SPLIT) {
-            stage_in<C, GT>(xr, gr, base, valid, gtid);
+            // both planes' loads in flight at once; LDS holds one plane at a time
+            v4f pr[E / 4], pi[E / 4];
+            load_rows<C, GT>(pr, xr, base, valid, gtid);
+            load_rows<C, GT>(pi, xi, base, valid, gtid);
+            put_rows<C, GT>(pr, gr, valid, gtid);
             xsync<T>();
             regs_from_natural<C>(vr, lr, t);
             xsync<T>();
-            stage_in<C, GT>(xi, gr, base, valid, gtid);
+            put_rows<C, GT>(pi, gr, valid, gtid);
             xsync<T>();
             regs_from_natural<C>(vi, lr, t);
         } else {
@@ -292,7 +298,7 @@ split_fft_lds_kernel(const float* xr, const float* xi, float* yr, float* yi, con
     if constexpr (C::F4OUT) {
         const int64_t rows_left = batch - (b0 + gslot0);
         const int valid = static_cast<int>(rows_left < GSLOTS ? (rows_left > 0 ? rows_left : 0) : GSLOTS) * N;
-        const int64_t base = (b0 + gslot0) * N;
+        const int64_t base = indirect ? row : (b0 + gslot0) * N;
         float* gr = lds + gslot0 * C::SLOT;
         if constexpr (C::SPLIT) {
             regs_to_natural<C>(vr, lr, t);
@@ -357,7 +363,7 @@ __device__ __forceinline__ void pin_regs(float (&v)[E])
 template <class C>
 __global__ void __launch_bounds__(C::THREADS) __attribute__((amdgpu_waves_per_eu(C::WPE)))
 split_fft_pf_kernel(const float* xr, const float* xi, float* yr, float* yi, const float2* __restrict__ tw,
-                    int64_t batch)
+                    int64_t batch, const int64_t* __restrict__ rows)
 {
     constexpr int M = C::M, RB = C::RB, TPW = C::TPW;
     constexpr int N = C::N, E = C::E, LT = C::LT, T = C::T, NP = C::NP;
@@ -390,6 +396,9 @@ split_fft_pf_kernel(const float* xr, const float* xi, float* yr, float* yi, cons
     }
 
     const int64_t blocks = (batch + TPW - 1) / TPW;
+    // rows (one transform per workgroup only): element offset of each transform
+    const bool indirect = TPW == 1 && rows != nullptr;
+    auto group_base = [&](int64_t blk) { return indirect ? rows[blk] : (blk * TPW + gslot0) * N; };
     // floats of the sync group's rows that exist in block blk
     auto group_valid = [&](int64_t blk) {
         const int64_t rows_left = batch - (blk * TPW + gslot0);
@@ -400,13 +409,13 @@ split_fft_pf_kernel(const float* xr, const float* xi, float* yr, float* yi, cons
     int64_t blk = blockIdx.x;
     if (blk < blocks) {
         const int valid = group_valid(blk);
-        const int64_t base = (blk * TPW + gslot0) * N;
+        const int64_t base = group_base(blk);
         load_rows<C, GT>(pr, xr, base, valid, gtid);
         load_rows<C, GT>(pi, xi, base, valid, gtid);
     }
     for (; blk < blocks; blk += gridDim.x) {
         const int valid = group_valid(blk);
-        const int64_t base = (blk * TPW + gslot0) * N;
+        const int64_t base = group_base(blk);
         // the position and twiddle addresses below depend only on t; an
         // opaque copy per iteration keeps the compiler from hoisting all of
         // them out of the loop into registers that the prefetch needs
@@ -440,7 +449,7 @@ split_fft_pf_kernel(const float* xr, const float* xi, float* yr, float* yi, cons
         const int64_t nblk = blk + gridDim.x;
         if (nblk < blocks) {
             const int nvalid = group_valid(nblk);
-            const int64_t nbase = (nblk * TPW + gslot0) * N;
+            const int64_t nbase = group_base(nblk);
             load_rows<C, GT>(pr, xr, nbase, nvalid, gtid);
             load_rows<C, GT>(pi, xi, nbase, nvalid, gtid);
         }
@@ -482,7 +491,7 @@ split_fft_pf_kernel(const float* xr, const float* xi, float* yr, float* yi, cons
             const int64_t b = blk * TPW + slot;
             if (b < batch) {
                 using Last = Pass<M, RB, NP - 1>;
-                const int64_t row = b * N;
+                const int64_t row = indirect ? base : b * N;
 #pragma unroll
                 for (int u = 0; u < E; ++u) {
                     const int64_t idx = row + position<LT, Last::S, Last::RP>(t, u);
@@ -571,8 +580,10 @@ split_fft_dif_kernel(const float* xr, const float* xi, float* yr, float* yi, con
 
 template <class C>
 hipError_t launch_dif(const float* xr, const float* xi, float* yr, float* yi, const float2* tw, int64_t batch,
-                      hipStream_t stream)
+                      const int64_t* rows, hipStream_t stream)
 {
+    if (rows)
+        return hipErrorInvalidValue;
     const int64_t blocks = (batch + C::TPW - 1) / C::TPW;
     if (blocks > INT_MAX)
         return hipErrorInvalidConfiguration;
@@ -602,8 +613,10 @@ __global__ void __launch_bounds__(256) split_fft_len1_kernel(const float* xr, co
 }
 
 hipError_t launch_len1(const float* xr, const float* xi, float* yr, float* yi, const float2*, int64_t batch,
-                       hipStream_t stream)
+                       const int64_t* rows, hipStream_t stream)
 {
+    if (rows)
+        return hipErrorInvalidValue;
     const int64_t blocks = (batch + 255) / 256;
     if (blocks > INT_MAX)
         return hipErrorInvalidConfiguration;
@@ -614,21 +627,25 @@ hipError_t launch_len1(const float* xr, const float* xi, float* yr, float* yi, c
 
 template <class C>
 hipError_t launch_lds(const float* xr, const float* xi, float* yr, float* yi, const float2* tw, int64_t batch,
-                      hipStream_t stream)
+                      const int64_t* rows, hipStream_t stream)
 {
+    if (rows && C::TPW != 1)
+        return hipErrorInvalidValue;
     const int64_t blocks = (batch + C::TPW - 1) / C::TPW;
     if (blocks > INT_MAX)
         return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(split_fft_lds_kernel<C>, dim3(static_cast<unsigned>(blocks)), dim3(C::THREADS), 0, stream,
-                       xr, xi, yr, yi, tw, batch);
+                       xr, xi, yr, yi, tw, batch, rows);
     return hipGetLastError();
 }
 
 // Workgroups of the persistent form: as many as can be resident at once.
 template <class C>
 hipError_t launch_pf(const float* xr, const float* xi, float* yr, float* yi, const float2* tw, int64_t batch,
-                     hipStream_t stream)
+                     const int64_t* rows, hipStream_t stream)
 {
+    if (rows && C::TPW != 1)
+        return hipErrorInvalidValue;
     const int64_t blocks = (batch + C::TPW - 1) / C::TPW;
     // resident workgroups per device, looked up once (launches are frequent)
     static std::atomic<int> resident_of[kMaxDevices];
@@ -652,7 +669,7 @@ hipError_t launch_pf(const float* xr, const float* xi, float* yr, float* yi, con
     }
     const int64_t grid = blocks < resident ? blocks : resident;
     hipLaunchKernelGGL(split_fft_pf_kernel<C>, dim3(static_cast<unsigned>(grid)), dim3(C::THREADS), 0, stream, xr,
-                       xi, yr, yi, tw, batch);
+                       xi, yr, yi, tw, batch, rows);
     return hipGetLastError();
 }
 
@@ -660,11 +677,11 @@ template <class C>
 constexpr Variant make_variant()
 {
     if constexpr (C::PF)
-        return Variant{C::M,   C::RB,  C::TPW,  C::THREADS, C::LDS_BYTES, C::SPLIT,
-                       C::NT,  C::TWL, C::WPE,  C::F4IO,    &launch_pf<C>, true};
+        return Variant{C::M,  C::RB,  C::TPW, C::THREADS, C::LDS_BYTES,  C::SPLIT,
+                       C::NT, C::TWL, C::WPE, C::F4IO,    &launch_pf<C>, true,     C::TPW == 1};
     else
-        return Variant{C::M,   C::RB,  C::TPW,  C::THREADS, C::LDS_BYTES, C::SPLIT,
-                       C::NT,  C::TWL, C::WPE,  C::F4IO,    &launch_lds<C>, false};
+        return Variant{C::M,  C::RB,  C::TPW, C::THREADS, C::LDS_BYTES,   C::SPLIT,
+                       C::NT, C::TWL, C::WPE, C::F4IO,    &launch_lds<C>, false,    C::TPW == 1};
 }
 
 // Compiled schedules per length; the first entry of each list is the default.
@@ -691,17 +708,20 @@ const Variant kV7[] = {V<7, 4, 32, Y, Y, 2, 4, 1, Y>(), V<7, 4, 16, _, Y, 2, 4, 
 const Variant kV8[] = {V<8, 4, 16, Y, Y, 2, 4, 1, Y>(), V<8, 4, 16, Y, Y, Y, 4, Y>(), V<8, 4, 32, Y, Y, 2, 4, 1, Y>(),
                        V<8, 4, 16, _, _, _, 1>()};
 const Variant kV9[] = {V<9, 4, 8, Y, Y, 2, 4, 2, Y>(), V<9, 4, 8, Y, Y, 2, 4, 1, Y>(), V<9, 4, 4, Y, Y, 2, 4, 2, Y>(),
-                       V<9, 4, 8, Y, Y, Y, 4, Y>(),    V<9, 4, 8, _, Y, Y, 1>()};
+                       V<9, 4, 8, Y, Y, Y, 4, Y>(),    V<9, 4, 8, _, Y, Y, 1>(),       V<9, 4, 8, Y, Y, 2, 4, 2>()};
 const Variant kV10[] = {V<10, 4, 4, _, Y, 2, 4, 2, Y>(), V<10, 4, 4, Y, Y, 2, 4, 2, Y>(), V<10, 4, 4, Y, Y, 1, 4, 2, Y>(),
                         V<10, 4, 4, Y, Y, 2, 3, 2, Y>(), V<10, 4, 8, Y, Y, 2, 3, 2, Y>(), V<10, 4, 2, Y, Y, 2, 4, 2, Y>(),
-                        V<10, 4, 8, Y, Y, 2, 4, 2, Y>(), V<10, 4, 8, Y, Y, Y, 4>(),       V<10, 5, 8, Y, Y, Y, 1>()};
-const Variant kV11[] = {V<11, 4, 1, Y, Y, 2, 4, 2, Y>(), V<11, 4, 2, Y, Y, 2, 4, 2, Y>(), V<11, 4, 1, _, Y, 2, 4, 2, Y>(),
-                        V<11, 4, 2, Y, Y, 2, 4>(),       V<11, 5, 4, Y, Y, Y, 1>()};
+                        V<10, 4, 8, Y, Y, 2, 4, 2, Y>(), V<10, 4, 8, Y, Y, Y, 4>(),       V<10, 5, 8, Y, Y, Y, 1>(),
+                        V<10, 4, 4, Y, Y, 2, 4, 2>(),    V<10, 4, 8, Y, Y, 2, 4, 2>()};
+const Variant kV11[] = {V<11, 4, 2, Y, Y, 2, 4, 2>(),    V<11, 4, 1, Y, Y, 2, 4, 2>(),    V<11, 4, 1, Y, Y, 2, 4, 2, Y>(),
+                        V<11, 4, 2, Y, Y, 2, 4, 2, Y>(), V<11, 4, 2, Y, Y, 2, 4>(),       V<11, 5, 4, Y, Y, Y, 1>()};
 const Variant kV12[] = {V<12, 4, 1, Y, Y, 2, 4, 2>(),    V<12, 5, 2, Y, Y, 2, 2>(),    V<12, 4, 1, Y, Y, 2, 3, 2, Y>(),
-                        V<12, 5, 2, Y, Y, Y, 2>(),       V<12, 4, 1, _, Y, 2, 4, 2>()};
-const Variant kV13[] = {V<13, 4, 1, Y, Y, 2, 4, 2, Y>(), V<13, 4, 1, Y, Y, 2, 1, 2>(), V<13, 5, 1, _, Y, _, 1>()};
+                        V<12, 5, 2, Y, Y, Y, 2>(),       V<12, 5, 1, Y, Y, 2, 2, 2>(), V<12, 4, 2, Y, Y, 2, 4, 2>()};
+const Variant kV13[] = {V<13, 5, 1, Y, Y, 2, 2, 2>(),    V<13, 4, 1, Y, Y, 2, 4, 2>(), V<13, 4, 1, Y, Y, 2, 4, 2, Y>(),
+                        V<13, 5, 1, Y, Y, 2, 4, 2>(),    V<13, 5, 1, _, Y, _, 1>()};
 const Variant kV14[] = {V<14, 4, 1, Y, Y, 2, 1, 2, Y>(), V<14, 4, 1, Y, Y, 3, 1, 2, Y>(), V<14, 5, 1, Y, Y, 2, 2, 2, Y>(),
-                        V<14, 4, 1, Y, Y, 2, 1, 2>()};
+                        V<14, 4, 1, Y, Y, 2, 1, 2>(),    V<14, 5, 1, Y, Y, 3, 4, 2>(),    V<14, 5, 1, Y, Y, 3, 2, 2>(),
+                        V<14, 5, 1, Y, Y, 2, 2, 2>()};
 const Variant kV15[] = {V<15, 5, 1, Y, Y, 3, 1, 2>(), V<15, 5, 1, Y, Y, _, 1>()};
 
 struct VariantList {

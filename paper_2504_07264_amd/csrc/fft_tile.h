@@ -41,6 +41,34 @@ __device__ __forceinline__ int64_t tile_row_offset(int r, int col0)
         return col0 + (static_cast<int64_t>(r) << TC::A);           // workspace row r, columns col0..
 }
 
+// tile_in in two steps, so that both planes' loads can be in flight at once:
+// this thread's 16-byte vectors of one plane of the tile ...
+template <class TC>
+__device__ __forceinline__ void tile_load(v4f (&r)[TC::E / 4], const float* src, int col0, int tid)
+{
+    constexpr int C4 = TC::C / 4;
+#pragma unroll
+    for (int c = 0; c < TC::E / 4; ++c) {
+        const int f4 = tid + c * TC::THREADS;
+        r[c] = load4<TC::PASS == 1>(src + tile_row_offset<TC>(f4 / C4, col0) + 4 * (f4 % C4));
+    }
+}
+
+// ... and into the LDS slots (layout of tile_in).
+template <class TC>
+__device__ __forceinline__ void tile_put(const v4f (&r)[TC::E / 4], float* lds, int tid)
+{
+    constexpr int C4 = TC::C / 4;
+#pragma unroll
+    for (int c = 0; c < TC::E / 4; ++c) {
+        const int f4 = tid + c * TC::THREADS;
+        const int row = f4 / C4, c4 = f4 % C4;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            lds[(4 * c4 + e) * TC::SLOT + lds_index(row)] = r[c][e];
+    }
+}
+
 // Tile (R rows x C columns, one plane) into LDS: column i in slot i, row r at
 // lds_index(r) of the slot.
 template <class TC>
@@ -126,15 +154,20 @@ __device__ __forceinline__ void tile_process(const float* xr, const float* xi, f
     float* area_i = TC::SPLIT ? lds : lds + C * TC::SLOT;
 
     float vr[E], vi[E];
-    tile_in<TC>(xr, lds, col0, tid);
     if constexpr (TC::SPLIT) {
+        // both planes' loads in flight at once; LDS holds one plane at a time
+        v4f pr[E / 4], pi[E / 4];
+        tile_load<TC>(pr, xr, col0, tid);
+        tile_load<TC>(pi, xi, col0, tid);
+        tile_put<TC>(pr, lds, tid);
         __syncthreads();
         tile_regs<TC>(vr, lr, t);
         __syncthreads();
-        tile_in<TC>(xi, lds, col0, tid);
+        tile_put<TC>(pi, lds, tid);
         __syncthreads();
         tile_regs<TC>(vi, lr, t);
     } else {
+        tile_in<TC>(xr, lds, col0, tid);
         tile_in<TC>(xi, area_i, col0, tid);
         __syncthreads();
         tile_regs<TC>(vr, lr, t);

@@ -31,23 +31,28 @@ namespace {
 template <class TC>
 __global__ void __launch_bounds__(TC::THREADS)
 split_fft_tile_kernel(const float* xr, const float* xi, float* yr, float* yi, const float2* __restrict__ tw,
-                      int tiles_per_transform)
+                      int tiles_per_transform, const int64_t* __restrict__ rows)
 {
     __shared__ float lds[TC::LDS_WORDS];
-    const int64_t base = static_cast<int64_t>(blockIdx.x / tiles_per_transform) * TC::N;
+    const int64_t t = blockIdx.x / tiles_per_transform;
+    // the workspace side is contiguous; the data side may be given per transform
+    const int64_t wbase = t * TC::N;
+    const int64_t dbase = rows ? rows[t] : wbase;
+    const int64_t ibase = TC::PASS == 1 ? dbase : wbase;
+    const int64_t obase = TC::PASS == 1 ? wbase : dbase;
     const int col0 = (blockIdx.x % tiles_per_transform) * TC::C;
-    tile_process<TC>(xr + base, xi + base, yr + base, yi + base, tw, col0, lds, threadIdx.x);
+    tile_process<TC>(xr + ibase, xi + ibase, yr + obase, yi + obase, tw, col0, lds, threadIdx.x);
 }
 
 template <class TC>
 hipError_t launch_tile(const float* xr, const float* xi, float* yr, float* yi, const float2* tw, int64_t batch,
-                       hipStream_t stream)
+                       const int64_t* rows, hipStream_t stream)
 {
     const int64_t blocks = batch * TC::TILES;
     if (blocks > INT_MAX)
         return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(split_fft_tile_kernel<TC>, dim3(static_cast<unsigned>(blocks)), dim3(TC::THREADS), 0, stream,
-                       xr, xi, yr, yi, tw, TC::TILES);
+                       xr, xi, yr, yi, tw, TC::TILES, rows);
     return hipGetLastError();
 }
 

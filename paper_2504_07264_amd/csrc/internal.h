@@ -24,9 +24,12 @@ struct Variant {
     int twl;      // twiddles of passes >= 1 in LDS: 0 no, 1 table slice, 2 quarter turn
     int wpe;      // occupancy hint (minimum waves per SIMD)
     int f4io;     // 16-byte global I/O staged through LDS: 0 no, 1 both ways, 2 loads
+    // rows: NULL for a contiguous [batch][n] layout, else the element offset
+    // of each transform (accepted when rows_ok)
     hipError_t (*launch)(const float* xr, const float* xi, float* yr, float* yi,
-                         const float2* tw, int64_t batch, hipStream_t stream);
-    bool pf = false;  // persistent workgroups, next block's loads prefetched
+                         const float2* tw, int64_t batch, const int64_t* rows, hipStream_t stream);
+    bool pf = false;       // persistent workgroups, next block's loads prefetched
+    bool rows_ok = false;  // takes per-transform offsets (one transform per workgroup)
 };
 
 // A two-pass schedule for large lengths: pass 1 runs stages 1..a on blocks of
@@ -38,10 +41,12 @@ struct TwoPass {
     int threads1, threads2;  // workgroup sizes
     int lds1, lds2;          // LDS bytes
     bool gf2;                // pass 2 lanes run over columns first
+    // rows: NULL for contiguous transforms, else the element offset of each
+    // transform in the data arrays (the workspace side is always contiguous)
     hipError_t (*pass1)(const float* xr, const float* xi, float* wr, float* wi, const float2* tw, int64_t batch,
-                        hipStream_t stream);
+                        const int64_t* rows, hipStream_t stream);
     hipError_t (*pass2)(const float* wr, const float* wi, float* yr, float* yi, const float2* tw, int64_t batch,
-                        hipStream_t stream);
+                        const int64_t* rows, hipStream_t stream);
 };
 
 // Compiled two-pass schedules for length 2^m (count returned through *count).
@@ -52,6 +57,11 @@ constexpr int kManyThreads = 512;         // workgroup size of the grouped kerne
 constexpr int kManyMinLog2N = 2;          // supported lengths 2^2 .. 2^16
 constexpr int kManyMaxLog2N = 16;
 constexpr int64_t kManyMaxN = int64_t{1} << kManyMaxLog2N;
+// default mode: lengths from 2^14 up run by the per-length kernels (single
+// pass at 2^14, two passes from 2^15 through chunks of at most this many bytes)
+constexpr int kManyPerLengthLog2N = 14;
+constexpr int kManyTwoPassLog2N = 15;
+constexpr int64_t kManyChunkBytes = int64_t{128} << 20;
 
 // One unit of work: `count` transforms of length 2^m taken from order[first..].
 struct ManyItem {
