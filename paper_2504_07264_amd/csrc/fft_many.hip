@@ -102,21 +102,31 @@ __device__ __noinline__ void many_group(Planes pl, const int64_t* __restrict__ o
     const int valid = valid_slots * N;
 
     float vr[E], vi[E];
-    // one plane at a time: 16-byte loads of each slot's row into LDS, then the
-    // registers of the first pass in bit-reversed order
+    // the 16-byte loads of both planes are issued first; then, one plane at a
+    // time, each slot's row goes into LDS and the registers of the first pass
+    // are read from it in bit-reversed order
+    v4f ld[2][E / 4];
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
         const float* src = p == 0 ? xr : xi;
 #pragma unroll
         for (int c = 0; c < E / 4; ++c) {
             const int f = 4 * (gtid + c * G::GT);
+            if (f < valid)
+                ld[p][c] = load4<true>(src + s_off[gslot0 + (f >> M)] + (f & (N - 1)));
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+#pragma unroll
+        for (int c = 0; c < E / 4; ++c) {
+            const int f = 4 * (gtid + c * G::GT);
             if (f < valid) {
-                const v4f v = load4<true>(src + s_off[gslot0 + (f >> M)] + (f & (N - 1)));
                 float* d = gl + (f >> M) * G::SLOT + lds_index(f & (N - 1));
-                d[0] = v[0];
-                d[1] = v[1];
-                d[2] = v[2];
-                d[3] = v[3];
+                d[0] = ld[p][c][0];
+                d[1] = ld[p][c][1];
+                d[2] = ld[p][c][2];
+                d[3] = ld[p][c][3];
             }
         }
         xsync<T>();
@@ -134,7 +144,7 @@ __device__ __noinline__ void many_group(Planes pl, const int64_t* __restrict__ o
 
     stages<E, LT, 0, Pass<M, RB, 0>::RP>(vr, vi, t, tw);
     if constexpr (G::NP > 1)
-        later_passes<M, RB, 1, true, E, TwTable<0>>(vr, vi, lr, lr, t, tw);
+        later_passes<M, RB, 1, true, E, TwQuarter<M>>(vr, vi, lr, lr, t, tw + N / 2);
 
     using Last = Pass<M, RB, G::NP - 1>;
 #pragma unroll
