@@ -405,9 +405,9 @@ split_dft_status split_dft_plan_describe(split_dft_plan_t plan, char* buf, size_
         const splitdft::TwoPass* t = plan->two;
         std::snprintf(buf, len,
                       "two-pass a=%d: pass1 %d blocks/wg %d threads lds=%d, pass2 %d columns/wg %d threads lds=%d "
-                      "gf=%d, chunk=%lld",
+                      "gf=%d ws=%s, chunk=%lld",
                       t->a, t->c1, t->threads1, t->lds1, t->c2, t->threads2, t->lds2, t->gf2 ? 1 : 0,
-                      static_cast<long long>(plan->chunk));
+                      t->wst ? "tiled" : "natural", static_cast<long long>(plan->chunk));
         return SPLIT_DFT_OK;
     }
     const splitdft::Variant* v = plan->variant;

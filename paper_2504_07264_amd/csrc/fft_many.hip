@@ -43,12 +43,13 @@ struct GroupShape {
     static constexpr int GSLOTS = GT / T;
 };
 
-using P1_14 = TileCfg<14, 8, 1, 4, 32, true>;
-using P2_14 = TileCfg<14, 8, 2, 4, 128, true, true>;
-using P1_15 = TileCfg<15, 8, 1, 4, 32, true>;
-using P2_15 = TileCfg<15, 8, 2, 4, 64, true, true>;
-using P1_16 = TileCfg<16, 8, 1, 4, 32, true>;
-using P2_16 = TileCfg<16, 8, 2, 4, 32, true, true>;
+// workspace in pass-2 tile order (see TileCfg)
+using P1_14 = TileCfg<14, 8, 1, 4, 32, true, false, 128>;
+using P2_14 = TileCfg<14, 8, 2, 4, 128, true, true, 128>;
+using P1_15 = TileCfg<15, 8, 1, 4, 32, true, false, 64>;
+using P2_15 = TileCfg<15, 8, 2, 4, 64, true, true, 64>;
+using P1_16 = TileCfg<16, 8, 1, 4, 32, true, false, 32>;
+using P2_16 = TileCfg<16, 8, 2, 4, 32, true, true, 32>;
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 template <int M>

@@ -11,9 +11,17 @@ namespace {
 // tid = g + C * t), so that the per-group twiddles of pass 2 (index
 // lo + (ql << A), lo = the group's column) are contiguous across a wave; the
 // groups then span waves and exchanges use workgroup barriers.
-template <int M_, int A_, int PASS_, int RB_, int C_, bool SPLIT_, bool GF_ = false>
+//
+// WSC: layout of the workspace between the passes.  0: natural position
+// order (pass 1 writes whole blocks, pass 2 reads rows of C columns strided by
+// 2^A).  WSC = pass 2's C: "tiled", position c 2^A + p of a transform at
+//     (p / WSC) (2^(M-A) WSC) + rev_(M-A)(c) WSC + p mod WSC,
+// so that one pass-2 tile (WSC columns, all rows) is one contiguous run and a
+// pass-1 tile (consecutive input columns k = rev(c)) writes runs of
+// C1 x WSC floats.  Pass 2 puts run row k at tile row rev_(M-A)(k).
+template <int M_, int A_, int PASS_, int RB_, int C_, bool SPLIT_, bool GF_ = false, int WSC_ = 0>
 struct TileCfg {
-    static constexpr int M = M_, A = A_, PASS = PASS_, RB = RB_, C = C_;
+    static constexpr int M = M_, A = A_, PASS = PASS_, RB = RB_, C = C_, WSC = WSC_;
     static constexpr bool SPLIT = SPLIT_, GF = GF_;
     static constexpr int N = 1 << M;
     static constexpr int MA = PASS == 1 ? A : M - A;  // log2 positions per group
@@ -28,8 +36,22 @@ struct TileCfg {
     static constexpr int TW_SHIFT = PASS == 1 ? 0 : A;
     static constexpr int GROUPS = PASS == 1 ? (1 << (M - A)) : (1 << A);  // per transform
     static constexpr int TILES = GROUPS / C;                               // per transform
+    static constexpr int R2 = 1 << (M - A);  // rows of a pass-2 column (blocks of pass 1)
     static_assert(C % 4 == 0 && E >= 4 && GROUPS % C == 0, "tile shape");
+    static_assert(WSC == 0 || (WSC % 4 == 0 && (1 << A) % WSC == 0 && (PASS == 1 || WSC == C)),
+                  "tiled workspace: pass 2's tile width");
 };
+
+// Tile row of source row r (the tiled workspace stores pass-2 rows in
+// bit-reversed order).
+template <class TC>
+__device__ __forceinline__ int tile_lds_row(int r)
+{
+    if constexpr (TC::PASS == 2 && TC::WSC > 0)
+        return rev_bits(r, TC::MA);
+    else
+        return r;
+}
 
 // Row r of the tile (C contiguous floats) in the source of the pass.
 template <class TC>
@@ -37,6 +59,8 @@ __device__ __forceinline__ int64_t tile_row_offset(int r, int col0)
 {
     if constexpr (TC::PASS == 1)
         return static_cast<int64_t>(r) * (TC::N >> TC::A) + col0;  // x row r, blocks col0..
+    else if constexpr (TC::WSC > 0)
+        return static_cast<int64_t>(col0) * TC::R + r * TC::C;      // tiled: one contiguous run
     else
         return col0 + (static_cast<int64_t>(r) << TC::A);           // workspace row r, columns col0..
 }
@@ -62,7 +86,7 @@ __device__ __forceinline__ void tile_put(const v4f (&r)[TC::E / 4], float* lds, 
 #pragma unroll
     for (int c = 0; c < TC::E / 4; ++c) {
         const int f4 = tid + c * TC::THREADS;
-        const int row = f4 / C4, c4 = f4 % C4;
+        const int row = tile_lds_row<TC>(f4 / C4), c4 = f4 % C4;
 #pragma unroll
         for (int e = 0; e < 4; ++e)
             lds[(4 * c4 + e) * TC::SLOT + lds_index(row)] = r[c][e];
@@ -80,9 +104,10 @@ __device__ __forceinline__ void tile_in(const float* src, float* lds, int col0, 
         const int f4 = tid + c * TC::THREADS;
         const int r = f4 / C4, c4 = f4 % C4;
         const v4f v = load4<TC::PASS == 1>(src + tile_row_offset<TC>(r, col0) + 4 * c4);
+        const int row = tile_lds_row<TC>(r);
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-            lds[(4 * c4 + e) * TC::SLOT + lds_index(r)] = v[e];
+            lds[(4 * c4 + e) * TC::SLOT + lds_index(row)] = v[e];
     }
 }
 
@@ -90,6 +115,22 @@ __device__ __forceinline__ void tile_in(const float* src, float* lds, int col0, 
 template <class TC>
 __device__ __forceinline__ void blocks_out(float* dst, const float* lds, int col0, int tid)
 {
+    if constexpr (TC::WSC > 0) {
+        // tiled workspace: for each group of WSC positions, the tile's C
+        // blocks (input columns col0 + i) form one run of C x WSC floats
+        constexpr int W4 = TC::WSC / 4;
+#pragma unroll
+        for (int c = 0; c < TC::E / 4; ++c) {
+            const int f4 = tid + c * TC::THREADS;
+            const int p4w = f4 % W4, rest = f4 / W4;
+            const int i = rest % TC::C, pg = rest / TC::C;
+            const float* s = lds + i * TC::SLOT + lds_index(pg * TC::WSC + 4 * p4w);
+            *reinterpret_cast<v4f*>(dst + static_cast<int64_t>(pg) * (TC::R2 * TC::WSC) +
+                                    static_cast<int64_t>(col0 + i) * TC::WSC + 4 * p4w) =
+                v4f{s[0], s[1], s[2], s[3]};
+        }
+        return;
+    }
     constexpr int R4 = TC::R / 4;
 #pragma unroll
     for (int c = 0; c < TC::E / 4; ++c) {
@@ -111,7 +152,8 @@ __device__ __forceinline__ void rows_out(float* dst, const float* lds, int col0,
         const int f4 = tid + c * TC::THREADS;
         const int r = f4 / C4, c4 = f4 % C4;
         const float* s = lds + (4 * c4) * TC::SLOT + lds_index(r);
-        store4<true>(dst + tile_row_offset<TC>(r, col0) + 4 * c4,
+        // the output is in natural order whatever the workspace layout
+        store4<true>(dst + col0 + (static_cast<int64_t>(r) << TC::A) + 4 * c4,
                      v4f{s[0], s[TC::SLOT], s[2 * TC::SLOT], s[3 * TC::SLOT]});
     }
 }

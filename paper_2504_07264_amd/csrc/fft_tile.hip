@@ -10,9 +10,11 @@
 //           bit a+s-1, so the positions lo + (p << a) (lo < 2^a) form
 //           2^a independent groups ("columns"); within column lo, local
 //           stage s is stage a+s with twiddle index q = lo + (ql << a).
-// The working vector between the passes lives in a workspace (row-major,
-// natural position order) that stays in the L2 / Infinity Cache when the
-// batch is processed in chunks.
+// The working vector between the passes lives in a workspace that the batch
+// is processed through in chunks; by default it is stored in pass-2 tile order
+// (see TileCfg), so that pass 1 writes and pass 2 reads long contiguous runs
+// and only the inherently strided sides (pass 1's gather of each block, pass
+// 2's natural-order output) use 128-byte segments.
 //
 // A workgroup handles a tile of C groups (columns) x R = 2^MA rows.  The tile
 // is loaded and stored with 16-byte vectors along rows (C contiguous floats)
@@ -56,34 +58,40 @@ hipError_t launch_tile(const float* xr, const float* xi, float* yr, float* yi, c
     return hipGetLastError();
 }
 
-template <int M, int A, int RB1, int C1, bool SPLIT1, int RB2, int C2, bool SPLIT2, bool GF2 = false>
+template <int M, int A, int RB1, int C1, bool SPLIT1, int RB2, int C2, bool SPLIT2, bool GF2 = false,
+          bool WST = false>
 constexpr TwoPass make_two_pass()
 {
-    using P1 = TileCfg<M, A, 1, RB1, C1, SPLIT1>;
-    using P2 = TileCfg<M, A, 2, RB2, C2, SPLIT2, GF2>;
+    constexpr int WSC = WST ? C2 : 0;
+    using P1 = TileCfg<M, A, 1, RB1, C1, SPLIT1, false, WSC>;
+    using P2 = TileCfg<M, A, 2, RB2, C2, SPLIT2, GF2, WSC>;
     return TwoPass{M,  A,  C1, C2, P1::THREADS, P2::THREADS, 4 * P1::LDS_WORDS, 4 * P2::LDS_WORDS, GF2,
-                   &launch_tile<P1>, &launch_tile<P2>};
+                   &launch_tile<P1>, &launch_tile<P2>, WST};
 }
 
 //                                   M   A  RB1 C1 SPLIT1 RB2 C2 SPLIT2 GF2
-const TwoPass kTwoPass14[] = {make_two_pass<14, 8, 4, 32, true, 4, 32, true, true>(),
-                              make_two_pass<14, 8, 4, 32, true, 4, 32, true>()};
-const TwoPass kTwoPass15[] = {make_two_pass<15, 8, 4, 32, true, 4, 32, true, true>(),
-                              make_two_pass<15, 8, 4, 32, true, 4, 32, true>(),
+const TwoPass kTwoPass14[] = {make_two_pass<14, 8, 4, 32, true, 4, 128, true, true, true>(),
+                              make_two_pass<14, 8, 4, 32, true, 4, 64, true, true, true>(),
+                              make_two_pass<14, 8, 4, 32, true, 4, 32, true, true>()};
+const TwoPass kTwoPass15[] = {make_two_pass<15, 8, 4, 32, true, 4, 64, true, true, true>(),
+                              make_two_pass<15, 8, 4, 64, true, 4, 64, true, true, true>(),
+                              make_two_pass<15, 8, 4, 32, true, 4, 128, true, true, true>(),
+                              make_two_pass<15, 8, 4, 32, true, 4, 32, true, true>(),
                               make_two_pass<15, 8, 4, 16, false, 4, 32, false>()};
-const TwoPass kTwoPass16[] = {make_two_pass<16, 8, 4, 32, true, 4, 32, true, true>(),
-                              make_two_pass<16, 8, 4, 32, true, 4, 32, true>(),
-                              make_two_pass<16, 8, 4, 16, false, 4, 16, false>(),
-                              make_two_pass<16, 8, 4, 32, true, 4, 64, true, true>()};
+const TwoPass kTwoPass16[] = {make_two_pass<16, 8, 4, 32, true, 4, 32, true, true, true>(),
+                              make_two_pass<16, 8, 4, 64, true, 4, 32, true, true, true>(),
+                              make_two_pass<16, 8, 4, 32, true, 4, 64, true, true, true>(),
+                              make_two_pass<16, 8, 4, 32, true, 4, 32, true, true>(),
+                              make_two_pass<16, 8, 4, 16, false, 4, 16, false>()};
 
 }  // namespace
 
 const TwoPass* two_pass_for(int m, int* count)
 {
     switch (m) {
-    case 14: *count = 2; return kTwoPass14;
-    case 15: *count = 3; return kTwoPass15;
-    case 16: *count = 4; return kTwoPass16;
+    case 14: *count = static_cast<int>(sizeof(kTwoPass14) / sizeof(kTwoPass14[0])); return kTwoPass14;
+    case 15: *count = static_cast<int>(sizeof(kTwoPass15) / sizeof(kTwoPass15[0])); return kTwoPass15;
+    case 16: *count = static_cast<int>(sizeof(kTwoPass16) / sizeof(kTwoPass16[0])); return kTwoPass16;
     default: *count = 0; return nullptr;
     }
 }

@@ -47,6 +47,7 @@ struct TwoPass {
                         const int64_t* rows, hipStream_t stream);
     hipError_t (*pass2)(const float* wr, const float* wi, float* yr, float* yi, const float2* tw, int64_t batch,
                         const int64_t* rows, hipStream_t stream);
+    bool wst;  // workspace in pass-2 tile order (else natural position order)
 };
 
 // Compiled two-pass schedules for length 2^m (count returned through *count).
