@@ -171,6 +171,33 @@ def mfma_vs_fp32(steps: int = 50, sets: int = 4):
     return out
 
 
+def dif_n1024(steps: int = 50, sets: int = 4):
+    """Forward N=1024 x 16384 through the decimation-in-frequency schedule
+    (eq. 9), same inputs as the headline: mean launch time from HIP events."""
+    import torch
+
+    from paper_2504_07264_amd import Plan, binding, inputs
+
+    w = inputs.HEADLINE_N1024
+    xr, xi = inputs.draw(w)
+    dev = torch.device("cuda", 0)
+    bufs = [(xr.to(dev), xi.to(dev), torch.empty_like(xr, device=dev), torch.empty_like(xi, device=dev))
+            for _ in range(sets)]
+    stream = torch.cuda.current_stream(dev)
+    with Plan(w.n, w.batch, binding.DIF) as plan:
+        for k in range(5):
+            plan.exec(*bufs[k % sets])
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for k in range(steps):
+            ev[k][0].record(stream)
+            plan.exec(*bufs[k % sets])
+            ev[k][1].record(stream)
+        torch.cuda.synchronize()
+        us = sum(a.elapsed_time(b) for a, b in ev) / steps * 1e3
+        return {"workload": "split_fft_n1024_b16384 forward, decimation in frequency (eq. 9)", "us": round(us, 2),
+                "GBps": round(16 * w.n * w.batch / us / 1e3, 1), "schedule": plan.describe()}
+
+
 def grad_n4096(steps: int = 30, sets: int = 3):
     """Forward + adjoint (the autograd step's two kernels) at N=4096 x 4096."""
     import torch
@@ -360,6 +387,8 @@ def main():
         out["mfma_vs_fp32"] = mfma_vs_fp32()
         torch.cuda.empty_cache()
     if not args.no_extra:
+        out["dif_n1024"] = dif_n1024()
+        torch.cuda.empty_cache()
         out["grad_n4096"] = grad_n4096()
         torch.cuda.empty_cache()
         out["ragged_grouped"] = ragged_grouped()

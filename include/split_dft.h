@@ -77,7 +77,7 @@ typedef enum {
  * (used by tuning). */
 /* Bit 24: evaluate through the decimation-in-frequency factorisation of
  * eq. (9), y_2N = S D^(1) W^(1) ... D^(m) W^(m) x_2N (stages m down to 1,
- * butterfly before rotation, the bit reversal last), FP32, n <= 2^13; results
+ * butterfly before rotation, the bit reversal last), FP32, n <= 2^14; results
  * are bit-identical to those factors applied in that order with the
  * operation forms above.  Other bits must be 0. */
 #define SPLIT_DFT_DIF (1u << 24)

@@ -201,7 +201,7 @@ split_dft_status split_dft_plan(split_dft_plan_t* out, int64_t n, int64_t batch,
         dif ? splitdft::dif_variants_for(m, &count) : splitdft::variants_for(m, &count);
     const splitdft::TwoPass* list2 = dif ? nullptr : splitdft::two_pass_for(m, &count2);
     if (dif && count == 0)
-        return fail(SPLIT_DFT_ERR_UNSUPPORTED, "the decimation-in-frequency schedule supports n <= 2^13");
+        return fail(SPLIT_DFT_ERR_UNSUPPORTED, "the decimation-in-frequency schedule supports n <= 2^14");
     const splitdft::Variant* v = nullptr;
     const splitdft::TwoPass* two = nullptr;
     if (vsel == 0) {

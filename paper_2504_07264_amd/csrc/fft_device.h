@@ -128,9 +128,12 @@ __device__ __forceinline__ void stages(float (&vr)[E], float (&vi)[E], int t, co
 // Stages S+RP .. S+1 of the decimation-in-frequency factorisation, eq. (9),
 // on the E registers of one thread (positions as in the DIT passes): for each
 // stage, highest first, the butterfly W^(i) (u + v, u - v) and then the
-// rotation D^(i) of the upper element by omega^(i,q), q as in stages().
-template <int E, int LT, int S, int RP>
-__device__ __forceinline__ void stages_dif(float (&vr)[E], float (&vi)[E], int t, const float2* __restrict__ tw)
+// rotation D^(i) of the upper element by omega^(i,q), q as in stages().  The
+// pass with S = 0 takes its uniform twiddles from the plan's table tw; the
+// other passes read theirs from the source TW at tws.
+template <int E, int LT, int S, int RP, class TW = TwTable<0>>
+__device__ __forceinline__ void stages_dif(float (&vr)[E], float (&vi)[E], int t, const float2* __restrict__ tw,
+                                           const float2* __restrict__ tws)
 {
 #pragma unroll
     for (int k = RP; k >= 1; --k) {
@@ -159,7 +162,7 @@ __device__ __forceinline__ void stages_dif(float (&vr)[E], float (&vi)[E], int t
             } else {
                 const int o = t + ((u >> RP) << LT);
                 const int q = (o & ((1 << S) - 1)) + ((u & (half - 1)) << S);
-                const float2 w = tw[(1 << (S + k - 1)) + q];
+                const float2 w = TW::get(tws, S + k, q);
                 rotate(dr, di, w.x, w.y);
             }
             vr[v] = dr;
@@ -221,10 +224,11 @@ struct PassD {
     static constexpr int S = M - RP0 - RB * P;
 };
 
-// DIF passes P, P+1, ...: exchange through LDS, then the pass's stages.
-template <int M, int RB, int P, bool SPLIT, int E>
+// DIF passes P, P+1, ...: exchange through LDS, then the pass's stages
+// (twiddle sources as in stages_dif).
+template <int M, int RB, int P, bool SPLIT, int E, class TW = TwTable<0>>
 __device__ __forceinline__ void later_passes_dif(float (&vr)[E], float (&vi)[E], float* lr, float* li, int t,
-                                                 const float2* __restrict__ tw)
+                                                 const float2* __restrict__ tw, const float2* __restrict__ tws)
 {
     if constexpr (P < PassD<M, RB, 0>::NP) {
         constexpr int LT = M - RB;
@@ -248,8 +252,8 @@ __device__ __forceinline__ void later_passes_dif(float (&vr)[E], float (&vi)[E],
             lds_get<E, LT, Cur::S, Cur::RP>(vi, li, t);
             xsync<T>();
         }
-        stages_dif<E, LT, Cur::S, Cur::RP>(vr, vi, t, tw);
-        later_passes_dif<M, RB, P + 1, SPLIT, E>(vr, vi, lr, li, t, tw);
+        stages_dif<E, LT, Cur::S, Cur::RP, TW>(vr, vi, t, tw, tws);
+        later_passes_dif<M, RB, P + 1, SPLIT, E, TW>(vr, vi, lr, li, t, tw, tws);
     }
 }
 

@@ -38,6 +38,7 @@
 
 #include <atomic>
 #include <climits>
+#include <type_traits>
 
 namespace splitdft {
 namespace {
@@ -60,10 +61,14 @@ constexpr int kMaxDevices = 64;
 //   PF     persistent workgroups with a grid-stride loop over blocks of TPW
 //          transforms; the 16-byte loads of the next block are issued into
 //          registers before the current block's passes (needs F4IO != 0)
-template <int M_, int RB_, int TPW_, bool SPLIT_, bool NT_, int TWL_, int WPE_, int F4IO_ = 0, bool PF_ = false>
+//   DIF    the decimation-in-frequency factorisation, eq. (9): registers of
+//          the first pass at natural positions (top bits first), stages m..1,
+//          the bit reversal applied on the way out
+template <int M_, int RB_, int TPW_, bool SPLIT_, bool NT_, int TWL_, int WPE_, int F4IO_ = 0, bool PF_ = false,
+          bool DIF_ = false>
 struct Cfg {
     static constexpr int M = M_, RB = RB_, TPW = TPW_, WPE = WPE_, TWL = TWL_;
-    static constexpr bool SPLIT = SPLIT_, NT = NT_, PF = PF_;
+    static constexpr bool SPLIT = SPLIT_, NT = NT_, PF = PF_, DIF = DIF_;
     static constexpr bool F4IN = F4IO_ != 0, F4OUT = F4IO_ == 1;
     static constexpr int F4IO = F4IO_;
     static constexpr int N = 1 << M;
@@ -154,22 +159,90 @@ __device__ __forceinline__ void stage_out(float* y, const float* area, int64_t b
 
 // Registers of the first pass from an LDS slot holding a transform in
 // natural order: position u + (t << RB) holds x[rev_LT(t) + (rev_RB(u) << LT)].
+// (DIF: position j of the first DIF pass holds x[j].)
 template <class C>
 __device__ __forceinline__ void regs_from_natural(float (&v)[C::E], const float* slot_area, int t)
 {
-    const int tb = rev_bits(t, C::LT);
+    if constexpr (C::DIF) {
+        using First = PassD<C::M, C::RB, 0>;
 #pragma unroll
-    for (int u = 0; u < C::E; ++u)
-        v[u] = slot_area[lds_index(tb + (rev_bits(u, C::RB) << C::LT))];
+        for (int u = 0; u < C::E; ++u)
+            v[u] = slot_area[lds_index(position<C::LT, First::S, First::RP>(t, u))];
+    } else {
+        const int tb = rev_bits(t, C::LT);
+#pragma unroll
+        for (int u = 0; u < C::E; ++u)
+            v[u] = slot_area[lds_index(tb + (rev_bits(u, C::RB) << C::LT))];
+    }
 }
 
+// The last pass's registers into an LDS slot in natural output order (DIF:
+// position j is output rev_M(j)).
 template <class C>
 __device__ __forceinline__ void regs_to_natural(const float (&v)[C::E], float* slot_area, int t)
 {
-    using Last = Pass<C::M, C::RB, C::NP - 1>;
+    if constexpr (C::DIF) {
+        using Last = PassD<C::M, C::RB, C::NP - 1>;
 #pragma unroll
-    for (int u = 0; u < C::E; ++u)
-        slot_area[lds_index(position<C::LT, Last::S, Last::RP>(t, u))] = v[u];
+        for (int u = 0; u < C::E; ++u)
+            slot_area[lds_index(rev_bits(position<C::LT, Last::S, Last::RP>(t, u), C::M))] = v[u];
+    } else {
+        using Last = Pass<C::M, C::RB, C::NP - 1>;
+#pragma unroll
+        for (int u = 0; u < C::E; ++u)
+            slot_area[lds_index(position<C::LT, Last::S, Last::RP>(t, u))] = v[u];
+    }
+}
+
+// Direct stores of the last pass (T > 1): DIT positions are natural output
+// indices; a DIF position j is output rev_M(j) (last pass on bits
+// 0..RB-1: rev_M(u + (t << RB)) = (rev_RB(u) << LT) + rev_LT(t), coalesced
+// over t).
+template <class C>
+__device__ __forceinline__ void store_last(float* yr, float* yi, int64_t row, const float (&vr)[C::E],
+                                           const float (&vi)[C::E], int t)
+{
+    if constexpr (C::DIF) {
+        using Last = PassD<C::M, C::RB, C::NP - 1>;
+#pragma unroll
+        for (int u = 0; u < C::E; ++u) {
+            const int64_t idx = row + rev_bits(position<C::LT, Last::S, Last::RP>(t, u), C::M);
+            store1<C::NT>(yr + idx, vr[u]);
+            store1<C::NT>(yi + idx, vi[u]);
+        }
+    } else {
+        using Last = Pass<C::M, C::RB, C::NP - 1>;
+#pragma unroll
+        for (int u = 0; u < C::E; ++u) {
+            const int64_t idx = row + position<C::LT, Last::S, Last::RP>(t, u);
+            store1<C::NT>(yr + idx, vr[u]);
+            store1<C::NT>(yi + idx, vi[u]);
+        }
+    }
+}
+
+// Every stage of the transform on the registers (first pass included), in the
+// order of eq. (6) (DIT) or eq. (9) (DIF).  lds_tw: the twiddles staged in LDS
+// (TWL 1 or 2), else unused.
+template <class C>
+__device__ __forceinline__ void run_stages(float (&vr)[C::E], float (&vi)[C::E], float* lr, float* li, int t,
+                                           const float2* __restrict__ tw, const float2* lds_tw)
+{
+    constexpr int M = C::M, RB = C::RB, E = C::E, LT = C::LT;
+    using TW = typename std::conditional<
+        (C::TW_LDS > 0), TwTable<E>,
+        typename std::conditional<(C::TWQ > 0 || C::TWL == 3), TwQuarter<(M >= 3 ? M : 3)>, TwTable<0>>::type>::type;
+    const float2* tws = (C::TW_LDS > 0 || C::TWQ > 0) ? lds_tw : (C::TWL == 3 ? tw + C::N / 2 : tw);
+    if constexpr (C::DIF) {
+        using First = PassD<M, RB, 0>;
+        stages_dif<E, LT, First::S, First::RP, TW>(vr, vi, t, tw, tws);
+        if constexpr (C::NP > 1)
+            later_passes_dif<M, RB, 1, C::SPLIT, E, TW>(vr, vi, lr, li, t, tw, tws);
+    } else {
+        stages<E, LT, 0, Pass<M, RB, 0>::RP>(vr, vi, t, tw);
+        if constexpr (C::NP > 1)
+            later_passes<M, RB, 1, C::SPLIT, E, TW>(vr, vi, lr, li, t, tws);
+    }
 }
 
 template <class C>
@@ -245,6 +318,8 @@ split_fft_lds_kernel(const float* xr, const float* xi, float* yr, float* yi, con
     } else if constexpr (T == 1) {
         // A whole transform per thread: natural-order vector loads; the bit
         // reversal is a renaming of registers.
+        // (DIF: no reversal on the way in; it is applied to the stores.)
+        constexpr int RIN = C::DIF ? 0 : M;
         if (active) {
             if constexpr (N >= 4) {
 #pragma unroll
@@ -252,21 +327,30 @@ split_fft_lds_kernel(const float* xr, const float* xi, float* yr, float* yi, con
                     const v4f a = load4<NT>(xr + row + 4 * c), z = load4<NT>(xi + row + 4 * c);
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
-                        vr[rev_bits(4 * c + e, M)] = a[e];
-                        vi[rev_bits(4 * c + e, M)] = z[e];
+                        vr[RIN ? rev_bits(4 * c + e, RIN) : 4 * c + e] = a[e];
+                        vi[RIN ? rev_bits(4 * c + e, RIN) : 4 * c + e] = z[e];
                     }
                 }
             } else {
 #pragma unroll
                 for (int n = 0; n < N; ++n) {
-                    vr[rev_bits(n, M)] = load1<NT>(xr + row + n);
-                    vi[rev_bits(n, M)] = load1<NT>(xi + row + n);
+                    vr[RIN ? rev_bits(n, RIN) : n] = load1<NT>(xr + row + n);
+                    vi[RIN ? rev_bits(n, RIN) : n] = load1<NT>(xi + row + n);
                 }
             }
         } else {
 #pragma unroll
             for (int u = 0; u < E; ++u)
                 vr[u] = vi[u] = 0.0f;
+        }
+    } else if constexpr (C::DIF) {
+        // position j of the first DIF pass holds x[j]: coalesced over t
+        using First = PassD<M, RB, 0>;
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            const int64_t idx = row + position<LT, First::S, First::RP>(t, u);
+            vr[u] = active ? load1<NT>(xr + idx) : 0.0f;
+            vi[u] = active ? load1<NT>(xi + idx) : 0.0f;
         }
     } else {
         // Position u + (t << RB) holds x[rev_M(u + (t << RB))]
@@ -280,20 +364,7 @@ split_fft_lds_kernel(const float* xr, const float* xi, float* yr, float* yi, con
         }
     }
 
-    stages<E, LT, 0, Pass<M, RB, 0>::RP>(vr, vi, t, tw);
-
-    if constexpr (NP > 1) {
-        if constexpr (C::TW_LDS > 0)
-            later_passes<M, RB, 1, C::SPLIT, E, TwTable<E>>(vr, vi, lr, li, t,
-                                                           reinterpret_cast<const float2*>(lds_tw4));
-        else if constexpr (C::TWQ > 0)
-            later_passes<M, RB, 1, C::SPLIT, E, TwQuarter<M>>(vr, vi, lr, li, t,
-                                                             reinterpret_cast<const float2*>(lds_tw4));
-        else if constexpr (C::TWL == 3)
-            later_passes<M, RB, 1, C::SPLIT, E, TwQuarter<M>>(vr, vi, lr, li, t, tw + N / 2);
-        else
-            later_passes<M, RB, 1, C::SPLIT, E, TwTable<0>>(vr, vi, lr, li, t, tw);
-    }
+    run_stages<C>(vr, vi, lr, li, t, tw, reinterpret_cast<const float2*>(lds_tw4));
 
     if constexpr (C::F4OUT) {
         const int64_t rows_left = batch - (b0 + gslot0);
@@ -320,28 +391,27 @@ split_fft_lds_kernel(const float* xr, const float* xi, float* yr, float* yi, con
 
     if (!active)
         return;
-    using Last = Pass<M, RB, NP - 1>;
     if constexpr (T == 1) {
+        // (DIF: output k is register rev_M(k).)
+        constexpr int ROUT = C::DIF ? M : 0;
+        auto reg = [](int k) { return ROUT ? rev_bits(k, ROUT) : k; };
         if constexpr (N >= 4) {
 #pragma unroll
             for (int c = 0; c < N / 4; ++c) {
-                store4<NT>(yr + row + 4 * c, v4f{vr[4 * c], vr[4 * c + 1], vr[4 * c + 2], vr[4 * c + 3]});
-                store4<NT>(yi + row + 4 * c, v4f{vi[4 * c], vi[4 * c + 1], vi[4 * c + 2], vi[4 * c + 3]});
+                store4<NT>(yr + row + 4 * c, v4f{vr[reg(4 * c)], vr[reg(4 * c + 1)], vr[reg(4 * c + 2)],
+                                                 vr[reg(4 * c + 3)]});
+                store4<NT>(yi + row + 4 * c, v4f{vi[reg(4 * c)], vi[reg(4 * c + 1)], vi[reg(4 * c + 2)],
+                                                 vi[reg(4 * c + 3)]});
             }
         } else {
 #pragma unroll
             for (int n = 0; n < N; ++n) {
-                store1<NT>(yr + row + n, vr[n]);
-                store1<NT>(yi + row + n, vi[n]);
+                store1<NT>(yr + row + n, vr[reg(n)]);
+                store1<NT>(yi + row + n, vi[reg(n)]);
             }
         }
     } else {
-#pragma unroll
-        for (int u = 0; u < E; ++u) {
-            const int64_t idx = row + position<LT, Last::S, Last::RP>(t, u);
-            store1<NT>(yr + idx, vr[u]);
-            store1<NT>(yi + idx, vi[u]);
-        }
+        store_last<C>(yr, yi, row, vr, vi, t);
     }
 }
 
@@ -454,19 +524,7 @@ split_fft_pf_kernel(const float* xr, const float* xi, float* yr, float* yi, cons
             load_rows<C, GT>(pi, xi, nbase, nvalid, gtid);
         }
 
-        stages<E, LT, 0, Pass<M, RB, 0>::RP>(vr, vi, t, tw);
-        if constexpr (NP > 1) {
-            if constexpr (C::TW_LDS > 0)
-                later_passes<M, RB, 1, C::SPLIT, E, TwTable<E>>(vr, vi, lr, li, t,
-                                                               reinterpret_cast<const float2*>(lds_tw4));
-            else if constexpr (C::TWQ > 0)
-                later_passes<M, RB, 1, C::SPLIT, E, TwQuarter<M>>(vr, vi, lr, li, t,
-                                                                 reinterpret_cast<const float2*>(lds_tw4));
-            else if constexpr (C::TWL == 3)
-                later_passes<M, RB, 1, C::SPLIT, E, TwQuarter<M>>(vr, vi, lr, li, t, tw + N / 2);
-            else
-                later_passes<M, RB, 1, C::SPLIT, E, TwTable<0>>(vr, vi, lr, li, t, tw);
-        }
+        run_stages<C>(vr, vi, lr, li, t, tw, reinterpret_cast<const float2*>(lds_tw4));
 
         if constexpr (C::F4OUT) {
             if constexpr (C::SPLIT) {
@@ -489,115 +547,10 @@ split_fft_pf_kernel(const float* xr, const float* xi, float* yr, float* yi, cons
         } else {
             // the last exchange ended with a sync, so the slots are free
             const int64_t b = blk * TPW + slot;
-            if (b < batch) {
-                using Last = Pass<M, RB, NP - 1>;
-                const int64_t row = indirect ? base : b * N;
-#pragma unroll
-                for (int u = 0; u < E; ++u) {
-                    const int64_t idx = row + position<LT, Last::S, Last::RP>(t, u);
-                    store1<NT>(yr + idx, vr[u]);
-                    store1<NT>(yi + idx, vi[u]);
-                }
-            }
+            if (b < batch)
+                store_last<C>(yr, yi, indirect ? base : b * N, vr, vi, t);
         }
     }
-}
-
-// Decimation-in-frequency schedule (eq. 9): natural-order loads of the first
-// pass's positions, stages m down to 1 (butterfly, then rotation), and the
-// bit reversal S applied last, folded into the store addresses.  In the last
-// pass (bits 0 .. RB-1) position u + (t << RB) goes to output
-// rev_M(u + (t << RB)) = (rev_RB(u) << LT) + rev_LT(t): coalesced over t.
-template <class C>
-__global__ void __launch_bounds__(C::THREADS) __attribute__((amdgpu_waves_per_eu(C::WPE)))
-split_fft_dif_kernel(const float* xr, const float* xi, float* yr, float* yi, const float2* __restrict__ tw,
-                     int64_t batch)
-{
-    constexpr int M = C::M, RB = C::RB, TPW = C::TPW;
-    constexpr int N = C::N, E = C::E, LT = C::LT, T = C::T, NP = C::NP;
-    constexpr bool NT = C::NT;
-    __shared__ float lds[C::XCH_WORDS];
-    const int tid = threadIdx.x;
-    const int slot = tid >> LT;
-    const int t = tid & (T - 1);
-    const int64_t b = static_cast<int64_t>(blockIdx.x) * TPW + slot;
-    const bool active = b < batch;
-    const int64_t row = b * N;
-    float* lr = lds + slot * C::SLOT;
-    float* li = C::SPLIT ? lr : lr + TPW * C::SLOT;
-    using First = PassD<M, RB, 0>;
-
-    float vr[E], vi[E];
-    if constexpr (T == 1 && N >= 4) {
-        if (active) {
-#pragma unroll
-            for (int c = 0; c < N / 4; ++c) {
-                const v4f a = load4<NT>(xr + row + 4 * c), z = load4<NT>(xi + row + 4 * c);
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    vr[4 * c + e] = a[e];
-                    vi[4 * c + e] = z[e];
-                }
-            }
-        } else {
-#pragma unroll
-            for (int u = 0; u < E; ++u)
-                vr[u] = vi[u] = 0.0f;
-        }
-    } else {
-#pragma unroll
-        for (int u = 0; u < E; ++u) {
-            const int64_t idx = row + position<LT, First::S, First::RP>(t, u);
-            vr[u] = active ? load1<NT>(xr + idx) : 0.0f;
-            vi[u] = active ? load1<NT>(xi + idx) : 0.0f;
-        }
-    }
-
-    stages_dif<E, LT, First::S, First::RP>(vr, vi, t, tw);
-    if constexpr (NP > 1)
-        later_passes_dif<M, RB, 1, C::SPLIT, E>(vr, vi, lr, li, t, tw);
-
-    if (!active)
-        return;
-    if constexpr (T == 1 && N >= 4) {
-#pragma unroll
-        for (int c = 0; c < N / 4; ++c) {
-            store4<NT>(yr + row + 4 * c, v4f{vr[rev_bits(4 * c, M)], vr[rev_bits(4 * c + 1, M)],
-                                             vr[rev_bits(4 * c + 2, M)], vr[rev_bits(4 * c + 3, M)]});
-            store4<NT>(yi + row + 4 * c, v4f{vi[rev_bits(4 * c, M)], vi[rev_bits(4 * c + 1, M)],
-                                             vi[rev_bits(4 * c + 2, M)], vi[rev_bits(4 * c + 3, M)]});
-        }
-    } else {
-        const int tb = rev_bits(t, LT);
-#pragma unroll
-        for (int u = 0; u < E; ++u) {
-            const int64_t idx = row + (rev_bits(u, RB) << LT) + tb;
-            store1<NT>(yr + idx, vr[u]);
-            store1<NT>(yi + idx, vi[u]);
-        }
-    }
-}
-
-template <class C>
-hipError_t launch_dif(const float* xr, const float* xi, float* yr, float* yi, const float2* tw, int64_t batch,
-                      const int64_t* rows, hipStream_t stream)
-{
-    if (rows)
-        return hipErrorInvalidValue;
-    const int64_t blocks = (batch + C::TPW - 1) / C::TPW;
-    if (blocks > INT_MAX)
-        return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(split_fft_dif_kernel<C>, dim3(static_cast<unsigned>(blocks)), dim3(C::THREADS), 0, stream,
-                       xr, xi, yr, yi, tw, batch);
-    return hipGetLastError();
-}
-
-template <int M, int RB, int TPW, bool SPLIT, bool NT, int WPE>
-constexpr Variant D()
-{
-    using C = Cfg<M, RB, TPW, SPLIT, NT, false, WPE>;
-    return Variant{C::M, C::RB, C::TPW, C::THREADS, C::LDS_BYTES, C::SPLIT, C::NT, false, C::WPE, false,
-                   &launch_dif<C>};
 }
 
 // N = 1: the transform is the identity.
@@ -693,6 +646,13 @@ constexpr Variant V()
     return make_variant<Cfg<M, RB, TPW, SPLIT, NT, TWL, WPE, F4IO, PF>>();
 }
 
+// decimation-in-frequency schedules (eq. 9)
+template <int M, int RB, int TPW, bool SPLIT, bool NT, int TWL, int WPE, int F4IO = 0, bool PF = false>
+constexpr Variant DV()
+{
+    return make_variant<Cfg<M, RB, TPW, SPLIT, NT, TWL, WPE, F4IO, PF, true>>();
+}
+
 constexpr bool Y = true, _ = false;
 //                      M   RB TPW SPLIT NT TWL WPE F4IO
 const Variant kV1[] = {V<1, 1, 256, _, _, _, 1>()};
@@ -735,28 +695,28 @@ struct VariantList {
 const VariantList kLists[] = {SDFT_L(kV0),  SDFT_L(kV1),  SDFT_L(kV2),  SDFT_L(kV3),  SDFT_L(kV4),  SDFT_L(kV5),
                               SDFT_L(kV6),  SDFT_L(kV7),  SDFT_L(kV8),  SDFT_L(kV9),  SDFT_L(kV10), SDFT_L(kV11),
                               SDFT_L(kV12), SDFT_L(kV13), SDFT_L(kV14), SDFT_L(kV15)};
-#undef SDFT_L
 
-// decimation-in-frequency schedules
-//                      M   RB TPW SPLIT NT WPE
-const Variant kD1[] = {D<1, 1, 256, false, false, 1>()};
-const Variant kD2[] = {D<2, 2, 256, false, false, 1>()};
-const Variant kD3[] = {D<3, 3, 256, false, false, 1>()};
-const Variant kD4[] = {D<4, 4, 64, false, false, 1>()};
-const Variant kD5[] = {D<5, 4, 64, false, false, 1>()};
-const Variant kD6[] = {D<6, 4, 32, false, false, 1>()};
-const Variant kD7[] = {D<7, 4, 16, false, false, 1>()};
-const Variant kD8[] = {D<8, 4, 16, true, false, 4>()};
-const Variant kD9[] = {D<9, 4, 8, true, true, 4>()};
-const Variant kD10[] = {D<10, 4, 4, true, true, 4>()};
-const Variant kD11[] = {D<11, 4, 2, true, true, 4>()};
-const Variant kD12[] = {D<12, 4, 1, true, true, 4>()};
-const Variant kD13[] = {D<13, 4, 1, true, true, 4>()};
+// decimation-in-frequency schedules; the first entry of each list is the default
+//                      M   RB TPW SPLIT NT TWL WPE F4IO PF
+const Variant kD1[] = {DV<1, 1, 256, _, _, _, 1>()};
+const Variant kD2[] = {DV<2, 2, 256, _, _, _, 1>()};
+const Variant kD3[] = {DV<3, 3, 256, _, _, _, 1>()};
+const Variant kD4[] = {DV<4, 4, 64, _, Y, _, 4, 1, Y>(), DV<4, 4, 64, _, _, _, 1>()};
+const Variant kD5[] = {DV<5, 4, 64, _, Y, 2, 4, 1, Y>(), DV<5, 4, 64, _, _, _, 1>()};
+const Variant kD6[] = {DV<6, 4, 64, _, Y, 2, 4, 1, Y>(), DV<6, 4, 32, _, _, _, 1>()};
+const Variant kD7[] = {DV<7, 4, 32, Y, Y, 2, 4, 1, Y>(), DV<7, 4, 16, _, _, _, 1>()};
+const Variant kD8[] = {DV<8, 4, 16, Y, Y, 2, 4, 1, Y>(), DV<8, 4, 16, Y, _, _, 4>()};
+const Variant kD9[] = {DV<9, 4, 8, Y, Y, 2, 4, 2, Y>(), DV<9, 4, 8, Y, Y, 2, 4, 1, Y>(), DV<9, 4, 8, Y, Y, _, 4>()};
+const Variant kD10[] = {DV<10, 4, 4, _, Y, 2, 4, 2, Y>(), DV<10, 4, 4, _, Y, 2, 4, 1, Y>(), DV<10, 4, 4, Y, Y, _, 4>()};
+// (the last DIF pass scatters its direct stores once T > 64: stage them)
+const Variant kD11[] = {DV<11, 4, 2, Y, Y, 2, 4, 1>(), DV<11, 4, 2, Y, Y, 2, 4, 2>(), DV<11, 4, 2, Y, Y, _, 4>()};
+const Variant kD12[] = {DV<12, 4, 1, Y, Y, 2, 4, 1>(), DV<12, 4, 2, Y, Y, 2, 4, 1>(), DV<12, 4, 1, Y, Y, _, 4>()};
+const Variant kD13[] = {DV<13, 5, 1, Y, Y, 2, 2, 1>(), DV<13, 4, 1, Y, Y, 2, 4, 1>()};
+const Variant kD14[] = {DV<14, 4, 1, Y, Y, 2, 1, 1, Y>(), DV<14, 4, 1, Y, Y, 2, 1, 1>()};
 
-#define SDFT_L(a) VariantList{a, static_cast<int>(sizeof(a) / sizeof(a[0]))}
-const VariantList kDLists[] = {SDFT_L(kV0),  SDFT_L(kD1),  SDFT_L(kD2),  SDFT_L(kD3), SDFT_L(kD4),
-                               SDFT_L(kD5),  SDFT_L(kD6),  SDFT_L(kD7),  SDFT_L(kD8), SDFT_L(kD9),
-                               SDFT_L(kD10), SDFT_L(kD11), SDFT_L(kD12), SDFT_L(kD13)};
+const VariantList kDLists[] = {SDFT_L(kV0),  SDFT_L(kD1),  SDFT_L(kD2),  SDFT_L(kD3),  SDFT_L(kD4),
+                               SDFT_L(kD5),  SDFT_L(kD6),  SDFT_L(kD7),  SDFT_L(kD8),  SDFT_L(kD9),
+                               SDFT_L(kD10), SDFT_L(kD11), SDFT_L(kD12), SDFT_L(kD13), SDFT_L(kD14)};
 #undef SDFT_L
 
 }  // namespace

@@ -96,7 +96,7 @@ def test_every_length_and_schedule(m):
         assert_within_tol(yr, yi, rr, ri, n)
 
 
-@pytest.mark.parametrize("m", range(10, 15))
+@pytest.mark.parametrize("m", range(4, 15))
 def test_persistent_schedules_many_blocks_per_workgroup(m):
     # The persistent schedules loop over blocks with a grid stride and
     # prefetch the next block: a batch of about 2^24 points gives every
@@ -104,7 +104,7 @@ def test_persistent_schedules_many_blocks_per_workgroup(m):
     n = 1 << m
     batch = ((1 << 24) // n + 3) | 1
     flags_list = []
-    for flags in all_variants(m)[1:]:
+    for flags in all_variants(m)[1:] + all_dif_variants(m)[1:]:
         with Plan(n, 1, flags) as p:
             if "persistent" in p.describe():
                 flags_list.append(flags)
@@ -112,12 +112,17 @@ def test_persistent_schedules_many_blocks_per_workgroup(m):
         pytest.skip("no persistent schedule for n = %d" % n)
     xr, xi = inputs.draw_planes(n, batch, "normal", 3000 + m)
     mr, mi = oracle.split_fft_f32(xr.numpy(), xi.numpy())
+    dr = di = None
     for flags in flags_list:
+        dif = bool(flags & binding.DIF)
+        if dif and dr is None:
+            dr, di = oracle.split_fft_dif_f32(xr.numpy(), xi.numpy())
         yr, yi = gpu_exec(n, batch, xr, xi, flags)
-        assert_bit_exact(yr, yi, mr, mi)
-        yr, yi = gpu_exec(n, batch, xr, xi, flags, adjoint=True)
-        ar, ai = oracle.split_adjoint_f32(xr.numpy(), xi.numpy())
-        assert_bit_exact(yr, yi, ar, ai)
+        assert_bit_exact(yr, yi, *((dr, di) if dif else (mr, mi)))
+        if not dif:
+            yr, yi = gpu_exec(n, batch, xr, xi, flags, adjoint=True)
+            ar, ai = oracle.split_adjoint_f32(xr.numpy(), xi.numpy())
+            assert_bit_exact(yr, yi, ar, ai)
 
 
 @pytest.mark.parametrize("m", [0, 1, 4, 7, 10, 12, 15, 16])
@@ -292,16 +297,31 @@ def test_single_pass_plans_need_no_workspace():
 
 
 # ------------------------------------------------------- decimation in frequency (eq. 9)
-@pytest.mark.parametrize("m", range(0, 14))
+def all_dif_variants(m):
+    out = [binding.DIF]
+    k = 0
+    while True:
+        try:
+            with Plan(1 << m, 1, binding.DIF | variant_flag(k)):
+                pass
+        except SplitDFTError:
+            break
+        out.append(binding.DIF | variant_flag(k))
+        k += 1
+    return out
+
+
+@pytest.mark.parametrize("m", range(0, 15))
 def test_dif_every_length(m):
     n = 1 << m
     batch = max(3, min(1000, (1 << 19) // n)) | 1
     xr, xi = inputs.draw_planes(n, batch, "normal", 3000 + m)
-    yr, yi = gpu_exec(n, batch, xr, xi, binding.DIF)
     mr, mi = oracle.split_fft_dif_f32(xr.numpy(), xi.numpy())
-    assert_bit_exact(yr, yi, mr, mi)
     rr, ri = oracle.split_fft(xr.double().numpy(), xi.double().numpy())
-    assert_within_tol(yr, yi, rr, ri, n)
+    for flags in all_dif_variants(m):
+        yr, yi = gpu_exec(n, batch, xr, xi, flags)
+        assert_bit_exact(yr, yi, mr, mi)
+        assert_within_tol(yr, yi, rr, ri, n)
     # the adjoint through the plane exchange
     ar, ai = gpu_exec(n, batch, xr, xi, binding.DIF, adjoint=True)
     hr, hi = oracle.split_fft_dif_f32(xi.numpy(), xr.numpy())
