@@ -35,6 +35,7 @@
 // The constant matrices are split on the host from FP64 values.
 #include "internal.h"
 
+#include <atomic>
 #include <climits>
 
 namespace splitdft {
@@ -159,10 +160,26 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// 16-byte loads of the TPI rows from b0 (zeros past the batch).
+template <int TPI>
+__device__ __forceinline__ void load_rows(v4f (&in)[TPI][2], const float* xr, const float* xi, int64_t b0,
+                                          int64_t batch, int lane)
+{
+#pragma unroll
+    for (int t = 0; t < TPI; ++t) {
+        if (b0 + t < batch) {
+            in[t][0] = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(xr + (b0 + t) * 256) + lane);
+            in[t][1] = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(xi + (b0 + t) * 256) + lane);
+        } else {
+            in[t][0] = in[t][1] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+    }
+}
+
 // TPI transforms per wave iteration; rows are staged through wave-private
 // LDS so that global loads and stores are 16-byte and fully coalesced.
 template <int MODE, int TPI>
-__global__ void __launch_bounds__(64 * kWaves)
+__global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(Prec<MODE>::PARTS == 2 ? 4 : 3)))
 split_fft256_mfma_kernel(const float* xr, const float* xi, float* yr, float* yi, const float* __restrict__ consts,
                          const float2* __restrict__ tw256, int64_t batch)
 {
@@ -188,23 +205,20 @@ split_fft256_mfma_kernel(const float* xr, const float* xi, float* yr, float* yi,
 
     // step-1 operand: lane (q, c) reads plane q >> 1 at n = 16 * (8 (q & 1) + r) + c
     const int a_off = (q >> 1) * kPlaneWords + pad256(128 * (q & 1) + c);
+    // the grid is resident: each wave loops with a stride and issues the
+    // next rows' loads before the current rows' arithmetic
+    v4f in[TPI][2];
+    if (wave * TPI < batch)
+        load_rows<TPI>(in, xr, xi, wave * TPI, batch, lane);
     for (int64_t b0 = wave * TPI; b0 < batch; b0 += nwaves * TPI) {
-        v4f in[TPI][2];
-#pragma unroll
-        for (int t = 0; t < TPI; ++t) {
-            if (b0 + t < batch) {
-                in[t][0] = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(xr + (b0 + t) * 256) + lane);
-                in[t][1] = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(xi + (b0 + t) * 256) + lane);
-            } else {
-                in[t][0] = in[t][1] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-            }
-        }
 #pragma unroll
         for (int t = 0; t < TPI; ++t)
 #pragma unroll
             for (int p = 0; p < 2; ++p)
                 *reinterpret_cast<v4f*>(my + (2 * t + p) * kPlaneWords + pad256(4 * lane)) = in[t][p];
         wave_lds_sync();
+        if (b0 + nwaves * TPI < batch)
+            load_rows<TPI>(in, xr, xi, b0 + nwaves * TPI, batch, lane);
 #pragma unroll
         for (int t = 0; t < TPI; ++t) {
             const float* src = my + 2 * t * kPlaneWords + a_off;
@@ -252,18 +266,39 @@ split_fft256_mfma_kernel(const float* xr, const float* xi, float* yr, float* yi,
     }
 }
 
+constexpr int kMaxDevices = 64;
+
 template <int MODE>
 hipError_t launch_mfma256(const float* xr, const float* xi, float* yr, float* yi, const float* consts,
                           const float2* tw256, int64_t batch, hipStream_t stream)
 {
     constexpr int TPI = 4;
-    // two iterations per wave so that the constant operands are reused
-    const int64_t per_block = kWaves * TPI * 2;
-    int64_t blocks = (batch + per_block - 1) / per_block;
-    if (blocks > INT_MAX)
-        blocks = INT_MAX;
-    hipLaunchKernelGGL((split_fft256_mfma_kernel<MODE, TPI>), dim3(static_cast<unsigned>(blocks)), dim3(64 * kWaves),
-                       0, stream, xr, xi, yr, yi, consts, tw256, batch);
+    auto kernel = split_fft256_mfma_kernel<MODE, TPI>;
+    // as many workgroups as can be resident (looked up once per device)
+    static std::atomic<int> resident_of[kMaxDevices];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    int resident = (dev >= 0 && dev < kMaxDevices) ? resident_of[dev].load(std::memory_order_relaxed) : 0;
+    if (resident <= 0) {
+        int cus = 0, per_cu = 0;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64 * kWaves, 0);
+        if (e != hipSuccess)
+            return e;
+        if (per_cu < 1 || cus < 1)
+            return hipErrorInvalidConfiguration;
+        resident = cus * per_cu;
+        if (dev >= 0 && dev < kMaxDevices)
+            resident_of[dev].store(resident, std::memory_order_relaxed);
+    }
+    const int64_t per_block = kWaves * TPI;
+    const int64_t blocks = (batch + per_block - 1) / per_block;
+    const int64_t grid = blocks < resident ? blocks : resident;
+    hipLaunchKernelGGL(kernel, dim3(static_cast<unsigned>(grid)), dim3(64 * kWaves), 0, stream, xr, xi, yr, yi, consts,
+                       tw256, batch);
     return hipGetLastError();
 }
 
