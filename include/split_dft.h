@@ -163,12 +163,13 @@ split_dft_status split_dft_twiddle_table(int m, float *c, float *s);
  * Each transform is the operation of split_dft_exec (eq. (6) applied in order,
  * bit-identical to it), and the adjoint that of split_dft_adjoint.
  *
- * Lengths up to 2^13 run in one persistent kernel launch: workgroups take
+ * The shorter lengths run in one persistent kernel launch: workgroups take
  * work items (a group of short transforms of one length) from a device
- * counter, largest first.  By default each length from 2^14 up runs in its
- * own launches of the single-length kernels, addressed through the
- * transforms' offsets (two passes through the plan's workspace from 2^15), all
- * on the caller's stream before the persistent launch; with
+ * counter, largest first.  By default each length from 2^12 up (a plan flag
+ * moves this threshold) runs in its own launches of the single-length kernels,
+ * addressed through the transforms' offsets (two passes through the plan's
+ * workspace from 2^15), all on the caller's stream before the persistent
+ * launch; with
  * SPLIT_DFT_MANY_ONE_KERNEL every length runs in the persistent kernel (one
  * transform of length >= 2^14 per work item, through a per-workgroup
  * workspace).  The counter returns to zero at the end of every launch, so
@@ -181,7 +182,9 @@ typedef struct split_dft_graph_s *split_dft_graph_t;
 
 /* flags: bits 0-7 precision (SPLIT_DFT_FP32 only); bits 8-15 kernel build
  * (0 = default, k = build k-1: 0 two workgroups per CU, 1 one); bits 16-23
- * workgroups per CU (0 = as many as fit); SPLIT_DFT_MANY_ONE_KERNEL.
+ * workgroups per CU (0 = as many as fit); SPLIT_DFT_MANY_ONE_KERNEL; bits
+ * 25-29: t, the lengths from 2^t up run in per-length launches (0 = the
+ * default 12; 10 <= t <= 17, 17 = none).
  * Allocates the device-side item list, offsets and twiddle table, and a
  * workspace: with SPLIT_DFT_MANY_ONE_KERNEL and some length >= 2^14, 512 KiB
  * per persistent workgroup; by default, when some length is 2^15 or more, one

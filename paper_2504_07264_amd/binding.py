@@ -280,10 +280,13 @@ def split_dft_adjoint(gr: torch.Tensor, gi: torch.Tensor, out=None):
 MANY_ONE_KERNEL = 1 << 24
 
 
-def many_flags(build: int = -1, workgroups_per_cu: int = 0, one_kernel: bool = False) -> int:
+def many_flags(build: int = -1, workgroups_per_cu: int = 0, one_kernel: bool = False,
+               per_length_from: int = 0) -> int:
     """Grouped-plan flag bits: kernel build (-1 = default), workgroups per CU
-    (0 = max), and whether lengths >= 2^14 also run in the persistent kernel."""
-    return ((int(build) + 1) << 8) + (int(workgroups_per_cu) << 16) + (MANY_ONE_KERNEL if one_kernel else 0)
+    (0 = max), whether every length runs in the persistent kernel, and log2 of
+    the shortest length run by per-length launches (0 = default)."""
+    return (((int(build) + 1) << 8) + (int(workgroups_per_cu) << 16) + (MANY_ONE_KERNEL if one_kernel else 0)
+            + (int(per_length_from) << 25))
 
 
 class ManyPlan:

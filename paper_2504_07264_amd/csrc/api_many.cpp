@@ -31,6 +31,7 @@ struct split_dft_many_s {
     int64_t points;
     int device;
     bool one_kernel;  // every length in the grouped kernel
+    bool large_items; // the persistent kernel meets lengths >= 2^14 (its larger build)
     std::vector<ManyLarge> large;
     int variant;  // grouped-kernel build
     int grid;     // persistent workgroups
@@ -209,7 +210,7 @@ split_dft_status many_launch(split_dft_many_t p, const float* xr, const float* x
     a.queue = p->d_queue;
     a.ws = p->d_ws;
     a.tw = p->d_tw;
-    const hipError_t e = splitdft::launch_many(p->variant, a, p->grid, stream);
+    const hipError_t e = splitdft::launch_many(p->variant, p->large_items, a, p->grid, stream);
     if (e != hipSuccess) {
         *msg = std::string("grouped kernel launch: ") + hipGetErrorString(e);
         return SPLIT_DFT_ERR_HIP;
@@ -234,9 +235,16 @@ split_dft_status split_dft_many_plan(split_dft_many_t* out, const int64_t* lengt
         return fail(SPLIT_DFT_ERR_NULL_POINTER, "out or lengths is NULL");
     if (count < 1 || count > INT32_MAX)
         return fail(SPLIT_DFT_ERR_INVALID_BATCH, "count must be in [1, 2^31 - 1]");
-    if ((flags & 0xffu) != SPLIT_DFT_FP32 || (flags >> 25) != 0)
+    if ((flags & 0xffu) != SPLIT_DFT_FP32 || (flags >> 30) != 0)
         return fail(SPLIT_DFT_ERR_UNSUPPORTED, "unsupported flags " + std::to_string(flags));
     const bool one_kernel = (flags & SPLIT_DFT_MANY_ONE_KERNEL) != 0;
+    // bits 25-29: log2 of the shortest length run by per-length launches
+    const int split_sel = static_cast<int>((flags >> 25) & 0x1fu);
+    if (split_sel != 0 && (split_sel < kManyPerLengthMinLog2N || split_sel > kManyMaxLog2N + 1))
+        return fail(SPLIT_DFT_ERR_UNSUPPORTED, "per-length threshold must be 2^" +
+                                                   std::to_string(kManyPerLengthMinLog2N) + " .. 2^" +
+                                                   std::to_string(kManyMaxLog2N + 1));
+    const int per_length_from = split_sel == 0 ? kManyPerLengthLog2N : split_sel;
     const int variant_sel = static_cast<int>((flags >> 8) & 0xffu);  // 0 = default build, k = build k-1
     const int wg_per_cu = static_cast<int>((flags >> 16) & 0xffu);   // 0 = as many as fit
     if (variant_sel > kManyKernelVariants)
@@ -254,7 +262,8 @@ split_dft_status split_dft_many_plan(split_dft_many_t* out, const int64_t* lengt
             return fail(SPLIT_DFT_ERR_INVALID_LENGTH,
                         "length " + std::to_string(k) + " = " + std::to_string(n) + " is not 2^m, 2 <= m <= 16");
         logs[static_cast<size_t>(k)] = m;
-        any_large = any_large || (m > 13 && one_kernel);
+        // lengths >= 2^14 that stay in the persistent kernel need its large build
+        any_large = any_large || (m > 13 && (one_kernel || m < per_length_from));
         if (offs[static_cast<size_t>(k)] > INT64_MAX / 8 - n)
             return fail(SPLIT_DFT_ERR_INVALID_BATCH, "total length overflows");
         offs[static_cast<size_t>(k) + 1] = offs[static_cast<size_t>(k)] + n;
@@ -277,7 +286,7 @@ split_dft_status split_dft_many_plan(split_dft_many_t* out, const int64_t* lengt
         size_t j = i;
         while (j < order.size() && logs[static_cast<size_t>(order[j])] == m)
             ++j;
-        if (!one_kernel && m >= kManyPerLengthLog2N) {
+        if (!one_kernel && m >= per_length_from) {
             LargeHost g{m, {}};
             for (size_t s = i; s < j; ++s)
                 g.rows.push_back(offs[static_cast<size_t>(order[s])]);
@@ -309,13 +318,14 @@ split_dft_status split_dft_many_plan(split_dft_many_t* out, const int64_t* lengt
     p->points = offs.back();
     p->offsets = offs;
     p->one_kernel = one_kernel;
+    p->large_items = any_large;
     p->variant = variant_sel == 0 ? 0 : variant_sel - 1;
     hipError_t e = hipGetDevice(&p->device);
     int cus = 0, per_cu = 0;
     if (e == hipSuccess)
         e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
     if (e == hipSuccess)
-        e = many_max_active_per_cu(p->variant, &per_cu);
+        e = many_max_active_per_cu(p->variant, any_large, &per_cu);
     if (e != hipSuccess) {
         free_many(p);
         return fail(SPLIT_DFT_ERR_HIP, std::string("device query: ") + hipGetErrorString(e));
@@ -344,20 +354,29 @@ split_dft_status split_dft_many_plan(split_dft_many_t* out, const int64_t* lengt
         e = upload(&p->d_queue, queue_init);
     if (e == hipSuccess)
         e = upload(&p->d_tw, tw);
-    if (e == hipSuccess && any_large) {
-        p->ws_bytes = static_cast<size_t>(p->grid) * 2 * static_cast<size_t>(kManyMaxN) * sizeof(float);
-        e = hipMalloc(&p->d_ws, p->ws_bytes);
-    }
-    // per-length kernels: schedules, offsets and the two-pass workspace
+    // one workspace serves both users, which run one after the other on the
+    // stream: the persistent kernel's per-workgroup regions (lengths >= 2^14
+    // in it) and the per-length two-pass chunks
+    size_t ws1 = any_large ? static_cast<size_t>(p->grid) * 2 * static_cast<size_t>(kManyMaxN) * sizeof(float) : 0;
     size_t ws2 = 0;
     for (LargeHost& h : large_host) {
         if (e != hipSuccess)
             break;
         ManyLarge g{h.m, static_cast<int64_t>(h.rows.size()), nullptr, nullptr, nullptr, 0};
+        // the length's default schedule if it takes per-transform offsets,
+        // else the first one that does
         const Variant* v = default_variant(h.m, g.count);
+        if (v && !v->rows_ok) {
+            int nv = 0;
+            const Variant* list = variants_for(h.m, &nv);
+            v = nullptr;
+            for (int k = 0; k < nv && !v; ++k)
+                if (list[k].rows_ok)
+                    v = &list[k];
+        }
         int c2 = 0;
         const TwoPass* two = two_pass_for(h.m, &c2);
-        if (h.m < kManyTwoPassLog2N && v && v->rows_ok) {
+        if (h.m < kManyTwoPassLog2N && v) {
             g.variant = v;
         } else if (two && c2 > 0) {
             g.two = &two[0];
@@ -373,8 +392,8 @@ split_dft_status split_dft_many_plan(split_dft_many_t* out, const int64_t* lengt
         e = upload(&g.d_rows, h.rows);
         p->large.push_back(g);
     }
-    if (e == hipSuccess && ws2 > 0) {
-        p->ws_bytes = ws2;
+    if (e == hipSuccess && std::max(ws1, ws2) > 0) {
+        p->ws_bytes = std::max(ws1, ws2);
         e = hipMalloc(&p->d_ws, p->ws_bytes);
     }
     if (e != hipSuccess) {

@@ -674,7 +674,8 @@ const Variant kV10[] = {V<10, 4, 4, _, Y, 2, 4, 2, Y>(), V<10, 4, 4, Y, Y, 2, 4,
                         V<10, 4, 8, Y, Y, 2, 4, 2, Y>(), V<10, 4, 8, Y, Y, Y, 4>(),       V<10, 5, 8, Y, Y, Y, 1>(),
                         V<10, 4, 4, Y, Y, 2, 4, 2>(),    V<10, 4, 8, Y, Y, 2, 4, 2>(),    V<10, 5, 8, Y, Y, 2, 2, 2>(),
                         V<10, 5, 4, Y, Y, 2, 2, 2>(),    V<10, 5, 8, _, Y, 2, 2, 2>(),    V<10, 5, 4, Y, Y, 2, 2, 2, Y>(),
-                        V<10, 5, 8, Y, Y, 2, 3, 2>()};
+                        V<10, 5, 8, Y, Y, 2, 3, 2>(),
+                        V<10, 4, 1, Y, Y, 2, 4, 2, Y>()};
 const Variant kV11[] = {V<11, 4, 2, Y, Y, 2, 4, 2>(),    V<11, 4, 1, Y, Y, 2, 4, 2>(),    V<11, 4, 1, Y, Y, 2, 4, 2, Y>(),
                         V<11, 4, 2, Y, Y, 2, 4, 2, Y>(), V<11, 4, 2, Y, Y, 2, 4>(),       V<11, 5, 4, Y, Y, Y, 1>()};
 const Variant kV12[] = {V<12, 4, 1, Y, Y, 2, 4, 2>(),    V<12, 5, 2, Y, Y, 2, 2>(),    V<12, 4, 1, Y, Y, 2, 3, 2, Y>(),

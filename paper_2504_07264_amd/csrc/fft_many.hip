@@ -60,8 +60,9 @@ constexpr int group_words_upto()
     else
         return cmax(GroupShape<M>::WORDS, group_words_upto<M - 1>());
 }
+constexpr int kGroupLdsWords = group_words_upto<13>();
 constexpr int kLdsWords =
-    cmax(group_words_upto<13>(),
+    cmax(kGroupLdsWords,
          cmax(cmax(P1_16::LDS_WORDS, P2_16::LDS_WORDS),
               cmax(cmax(P2_15::LDS_WORDS, P2_14::LDS_WORDS), cmax(P1_15::LDS_WORDS, P1_14::LDS_WORDS))));
 static_assert(P1_16::THREADS == kMT && P2_16::THREADS == kMT && P1_15::THREADS == kMT && P2_15::THREADS == kMT &&
@@ -77,10 +78,10 @@ struct Planes {
 };
 
 // Group item: transforms order[first .. first + count) of length 2^M.
-template <int M, int WPE>
-__device__ __noinline__ void many_group(Planes pl, const int64_t* __restrict__ offsets,
-                                           const int32_t* __restrict__ order, int64_t first, int count,
-                                           const float2* __restrict__ tw, float* lds, int64_t* s_off, int tid)
+template <int M>
+__device__ __forceinline__ void many_group_body(Planes pl, const int64_t* __restrict__ offsets,
+                                                const int32_t* __restrict__ order, int64_t first, int count,
+                                                const float2* __restrict__ tw, float* lds, int64_t* s_off, int tid)
 {
     using G = GroupShape<M>;
     constexpr int E = G::E, LT = G::LT, T = G::T, RB = G::RB, N = G::N;
@@ -169,6 +170,16 @@ __device__ __noinline__ void many_group(Planes pl, const int64_t* __restrict__ o
     __syncthreads();
 }
 
+// Out of line: each length's item keeps its own register allocation (inlined
+// into one dispatch, the twelve lengths' code would share, and spill, one).
+template <int M, int WPE>
+__device__ __noinline__ void many_group(Planes pl, const int64_t* __restrict__ offsets,
+                                        const int32_t* __restrict__ order, int64_t first, int count,
+                                        const float2* __restrict__ tw, float* lds, int64_t* s_off, int tid)
+{
+    many_group_body<M>(pl, offsets, order, first, count, tw, lds, s_off, tid);
+}
+
 // Large item: one transform through this workgroup's workspace region.
 template <class P1, class P2, int WPE>
 __device__ __noinline__ void many_large(Planes pl, int64_t off, float* ws, const float2* __restrict__ tw,
@@ -194,14 +205,16 @@ __device__ __noinline__ void many_large(Planes pl, int64_t off, float* ws, const
 
 // WPE: minimum waves per SIMD the register allocation must allow (1 = no
 // limit, one workgroup per CU; 4 = two workgroups per CU, 128 VGPRs).
-template <int WPE>
+// LARGE: whether items of length >= 2^14 can occur (else their code, LDS and
+// registers are left out).
+template <int WPE, bool LARGE>
 __global__ void __launch_bounds__(kMT) __attribute__((amdgpu_waves_per_eu(WPE)))
 split_fft_many_kernel(const float* in_r0, const float* in_i0, float* out_r0, float* out_i0, const float* in_r1,
                       const float* in_i1, float* out_r1, float* out_i1, const int64_t* __restrict__ offsets,
                       const int32_t* __restrict__ order, const ManyItem* __restrict__ items, int nitems, int* queue,
                       float* ws, const float2* __restrict__ tw)
 {
-    __shared__ float lds[kLdsWords];
+    __shared__ float lds[LARGE ? kLdsWords : kGroupLdsWords];
     __shared__ int64_t s_off[kMT];
     __shared__ int s_item;
     const int tid = threadIdx.x;
@@ -238,9 +251,18 @@ split_fft_many_kernel(const float* in_r0, const float* in_i0, float* out_r0, flo
             SDFT_GROUP(12)
             SDFT_GROUP(13)
 #undef SDFT_GROUP
-        case 14: many_large<P1_14, P2_14, WPE>(pl, offsets[order[first]], ws, tw, lds, tid); break;
-        case 15: many_large<P1_15, P2_15, WPE>(pl, offsets[order[first]], ws, tw, lds, tid); break;
-        case 16: many_large<P1_16, P2_16, WPE>(pl, offsets[order[first]], ws, tw, lds, tid); break;
+        case 14:
+            if constexpr (LARGE)
+                many_large<P1_14, P2_14, WPE>(pl, offsets[order[first]], ws, tw, lds, tid);
+            break;
+        case 15:
+            if constexpr (LARGE)
+                many_large<P1_15, P2_15, WPE>(pl, offsets[order[first]], ws, tw, lds, tid);
+            break;
+        case 16:
+            if constexpr (LARGE)
+                many_large<P1_16, P2_16, WPE>(pl, offsets[order[first]], ws, tw, lds, tid);
+            break;
         default: break;
         }
     }
@@ -254,20 +276,26 @@ split_fft_many_kernel(const float* in_r0, const float* in_i0, float* out_r0, flo
     }
 }
 
+template <bool LARGE>
+auto many_kernel(int variant)
+{
+    return variant == 0 ? split_fft_many_kernel<4, LARGE> : split_fft_many_kernel<1, LARGE>;
+}
+
 }  // namespace
 
-hipError_t launch_many(int variant, const ManyArgs& a, int grid, hipStream_t stream)
+hipError_t launch_many(int variant, bool large, const ManyArgs& a, int grid, hipStream_t stream)
 {
-    auto k = variant == 0 ? split_fft_many_kernel<4> : split_fft_many_kernel<1>;
+    auto k = large ? many_kernel<true>(variant) : many_kernel<false>(variant);
     hipLaunchKernelGGL(k, dim3(static_cast<unsigned>(grid)), dim3(kMT), 0, stream, a.in_r[0], a.in_i[0], a.out_r[0],
                        a.out_i[0], a.in_r[1], a.in_i[1], a.out_r[1], a.out_i[1], a.offsets, a.order, a.items,
                        a.nitems, a.queue, a.ws, a.tw);
     return hipGetLastError();
 }
 
-hipError_t many_max_active_per_cu(int variant, int* blocks)
+hipError_t many_max_active_per_cu(int variant, bool large, int* blocks)
 {
-    auto k = variant == 0 ? split_fft_many_kernel<4> : split_fft_many_kernel<1>;
+    auto k = large ? many_kernel<true>(variant) : many_kernel<false>(variant);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k, kMT, 0);
 }
 

@@ -58,9 +58,11 @@ constexpr int kManyThreads = 512;         // workgroup size of the grouped kerne
 constexpr int kManyMinLog2N = 2;          // supported lengths 2^2 .. 2^16
 constexpr int kManyMaxLog2N = 16;
 constexpr int64_t kManyMaxN = int64_t{1} << kManyMaxLog2N;
-// default mode: lengths from 2^14 up run by the per-length kernels (single
-// pass at 2^14, two passes from 2^15 through chunks of at most this many bytes)
-constexpr int kManyPerLengthLog2N = 14;
+// default mode: lengths from 2^12 up run by the per-length kernels (single
+// pass to 2^14, two passes from 2^15 through chunks of at most this many
+// bytes); the threshold is a plan flag, from 2^10
+constexpr int kManyPerLengthLog2N = 12;
+constexpr int kManyPerLengthMinLog2N = 10;
 constexpr int kManyTwoPassLog2N = 15;
 constexpr int64_t kManyChunkBytes = int64_t{128} << 20;
 
@@ -90,8 +92,9 @@ struct ManyArgs {
 // Grouped-kernel builds: 0 = 128-VGPR budget (two workgroups per CU),
 // 1 = no register limit (one workgroup per CU).
 constexpr int kManyKernelVariants = 2;
-hipError_t launch_many(int variant, const ManyArgs& args, int grid, hipStream_t stream);
-hipError_t many_max_active_per_cu(int variant, int* blocks);
+// large: items of length >= 2^14 may occur (the build that carries them)
+hipError_t launch_many(int variant, bool large, const ManyArgs& args, int grid, hipStream_t stream);
+hipError_t many_max_active_per_cu(int variant, bool large, int* blocks);
 int many_items_per_group(int m);
 
 // All compiled variants for length 2^m (count returned through *count).

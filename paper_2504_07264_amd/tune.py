@@ -106,23 +106,24 @@ def tune_length(n: int, batch: int, iters: int = 20, sets: int = 3):
 
 def tune_many(lengths, iters: int = 5):
     """Time the grouped kernel builds, workgroups-per-CU settings and the
-    placement of lengths >= 2^14 (per-length kernels or the persistent kernel)
-    on a forward + adjoint graph of the ragged batch; returns (best flags,
-    timings)."""
+    split between per-length launches and the persistent kernel (threshold, or
+    every length in the persistent kernel) on a forward + adjoint graph of the
+    ragged batch; returns (best flags, timings)."""
     dev = torch.device("cuda", torch.cuda.current_device())
     total = int(sum(int(n) for n in lengths))
     planes = [torch.randn(total, device=dev) for _ in range(8)]
+    candidates = [(b, w, False, 0) for b in range(2) for w in (0, 1)]
+    candidates += [(0, 0, False, t) for t in (11, 13, 14)]
+    candidates += [(b, w, True, 0) for b in range(2) for w in (0, 1)]
     timings = {}
-    for one_kernel in (False, True):
-        for build in range(2):
-            for wpc in (0, 1):
-                flags = many_flags(build, wpc, one_kernel)
-                with ManyPlan(lengths, flags) as p:
-                    g = p.graph(*planes)
-                    us = _time(lambda k: g.launch(), iters, warmup=1)
-                    g.close()
-                    timings[flags] = {"us": round(us, 1), "workgroups": p.info()["workgroups"],
-                                      "one_kernel": one_kernel}
+    for build, wpc, one_kernel, split in candidates:
+        flags = many_flags(build, wpc, one_kernel, split)
+        with ManyPlan(lengths, flags) as p:
+            g = p.graph(*planes)
+            us = _time(lambda k: g.launch(), iters, warmup=1)
+            g.close()
+            timings[flags] = {"us": round(us, 1), "workgroups": p.info()["workgroups"], "one_kernel": one_kernel,
+                              "per_length_from": split}
     best = min(timings, key=lambda f: timings[f]["us"])
     return best, timings
 

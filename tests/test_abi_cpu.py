@@ -138,7 +138,9 @@ def test_many_plan_validates_before_any_hip_call(L):
     assert L.split_dft_many_plan(ctypes.byref(h), a.ctypes.data, 0, 0) == 2
     assert L.split_dft_many_plan(ctypes.byref(h), a.ctypes.data, 2, 1) == 6
     assert L.split_dft_many_plan(ctypes.byref(h), a.ctypes.data, 2, 9 << 8) == 6
-    assert L.split_dft_many_plan(ctypes.byref(h), a.ctypes.data, 2, 1 << 25) == 6
+    assert L.split_dft_many_plan(ctypes.byref(h), a.ctypes.data, 2, 1 << 30) == 6
+    assert L.split_dft_many_plan(ctypes.byref(h), a.ctypes.data, 2, 9 << 25) == 6   # threshold below 2^10
+    assert L.split_dft_many_plan(ctypes.byref(h), a.ctypes.data, 2, 18 << 25) == 6  # above 2^17
     assert L.split_dft_many_plan(None, a.ctypes.data, 2, 0) == 3
     assert L.split_dft_many_plan(ctypes.byref(h), None, 2, 0) == 3
     bogus = ctypes.c_void_p(0x1000)

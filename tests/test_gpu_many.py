@@ -53,14 +53,17 @@ def mixed_lengths(seed, per_len=3, mmin=2, mmax=16):
     return ls
 
 
-@pytest.mark.parametrize("build,one_kernel", [(-1, False), (1, False), (-1, True), (1, True)])
-def test_mixed_lengths_forward_adjoint_both(build, one_kernel):
+# (kernel build, every length in the persistent kernel, per-length threshold)
+@pytest.mark.parametrize("build,one_kernel,split", [(-1, False, 0), (1, False, 0), (-1, True, 0), (1, True, 0),
+                                                    (-1, False, 10), (-1, False, 15), (-1, False, 17)])
+def test_mixed_lengths_forward_adjoint_both(build, one_kernel, split):
     lengths = mixed_lengths(5)
     total = int(lengths.sum())
     g = torch.Generator().manual_seed(6)
     xr, xi, gr, gi = [torch.randn(total, generator=g) for _ in range(4)]
-    say("  grouped build=%d one_kernel=%s count=%d points=%d" % (build, one_kernel, len(lengths), total))
-    with ManyPlan(lengths, many_flags(build, one_kernel=one_kernel)) as p:
+    say("  grouped build=%d one_kernel=%s split=%d count=%d points=%d"
+        % (build, one_kernel, split, len(lengths), total))
+    with ManyPlan(lengths, many_flags(build, one_kernel=one_kernel, per_length_from=split)) as p:
         offs = p.offsets
         assert offs[-1] == total
         fwd = mirror_ragged(lengths, offs, xr.numpy(), xi.numpy(), range(len(lengths)))

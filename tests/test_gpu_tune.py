@@ -29,10 +29,11 @@ def test_tune_many_small(tmp_path):
     path = str(tmp_path / "tune.json")
     lengths = [16, 1 << 14, 256, 1 << 16, 64, 4096] * 3
     best, timings = tune.tune_many(lengths, iters=2)
-    # two kernel builds x two workgroups-per-CU settings x two placements of
-    # the lengths >= 2^14
-    assert best in timings and len(timings) == 8
+    # kernel builds x workgroups-per-CU settings, per-length thresholds, and
+    # every length in the persistent kernel
+    assert best in timings and len(timings) == 11
     assert {v["one_kernel"] for v in timings.values()} == {False, True}
+    assert {v["per_length_from"] for v in timings.values()} == {0, 11, 13, 14}
     tune.record(tune.ragged_key(lengths), best, timings, path)
     with tune.tuned_many_plan(lengths, path) as p:
         assert p.points == sum(lengths)
