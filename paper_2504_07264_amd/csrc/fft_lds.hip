@@ -5,7 +5,8 @@
 // (real plane, imaginary plane) and applies the factors of eq. (6) of the
 // paper (Section III) in order:
 //
-//   S        bit reversal: folded into the global-load addresses;
+//   S        bit reversal: folded into the global-load addresses, or into
+//            the LDS reads of the first pass when the rows are staged;
 //   D^(i)    the upper element of each pair at distance 2^(i-1) is rotated
 //            by omega^(i,q) = [[c, s], [-s, c]];
 //   W^(i)    butterfly (u + v, u - v) on each plane separately.
@@ -29,11 +30,19 @@
 // (o >> S) = 0 and j = o + (uu << S), so the stores are coalesced too.
 //
 // Every rotation is fmaf(c, ar, s*ai), fmaf(c, ai, -(s*ar)) with FP32
-// twiddles from the plan's table (entry 2^(i-1) + q holds omega^(i,q)); in the
-// first pass the twiddles with q = 0 (identity) and angle pi/2 (swap and
-// negate) are applied as such, which gives the same values as the general
+// twiddles from the plan's table (entry 2^(i-1) + q holds omega^(i,q)), or
+// from an equal-valued copy (a table slice or the quarter-turn table in LDS);
+// in the first pass the twiddles with q = 0 (identity) and angle pi/2 (swap
+// and negate) are applied as such, which gives the same values as the general
 // form with the table's exact 1 and 0.  The results therefore equal, bit for
 // bit, the factors of eq. (6) applied one after the other in FP32.
+//
+// Two kernels share this scheme: split_fft_lds_kernel (one block of TPW
+// transforms per workgroup) and split_fft_pf_kernel (a resident grid looping
+// over blocks, prefetching the next block's rows).  The same kernels also run
+// the decimation-in-frequency factorisation of eq. (9) (Cfg::DIF).  Each
+// compiled schedule is one Cfg; every length has a list of them, the first
+// being the default.
 #include "fft_device.h"
 
 #include <atomic>

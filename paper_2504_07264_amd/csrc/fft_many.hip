@@ -1,5 +1,7 @@
 // Grouped execution: many split-format transforms of different power-of-two
 // lengths (a ragged batch), forward and adjoint, in one persistent launch.
+// (By default the plan sends its longer lengths to the single-length kernels
+// instead; this kernel then only meets group items.)
 //
 // Each transform k occupies [offset_k, offset_k + N_k) of every plane.  The
 // host sorts the transforms by length and cuts the work into items:
