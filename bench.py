@@ -74,6 +74,40 @@ def measured_traffic():
         return None
 
 
+def device_info(dev):
+    """Name, architecture, CU count, HIP version and (best effort, from sysfs)
+    the current and highest shader / memory clock levels of the device."""
+    import torch
+
+    props = torch.cuda.get_device_properties(dev)
+    info = {"name": props.name, "arch": getattr(props, "gcnArchName", None), "cus": props.multi_processor_count,
+            "hip": getattr(torch.version, "hip", None)}
+    try:
+        pci = "%04x:%02x:%02x.0" % (props.pci_domain_id, props.pci_bus_id, props.pci_device_id)
+    except AttributeError:
+        return info
+    for key, fname in (("sclk", "pp_dpm_sclk"), ("mclk", "pp_dpm_mclk")):
+        try:
+            with open("/sys/bus/pci/devices/%s/%s" % (pci, fname)) as f:
+                levels = [ln.split(":", 1)[1].strip() for ln in f.read().splitlines() if ":" in ln]
+        except OSError:
+            continue
+        cur = [lv.rstrip("*").strip() for lv in levels if lv.endswith("*")]
+        info[key] = {"current": cur[0] if cur else None, "max": levels[-1].rstrip("*").strip() if levels else None}
+    return info
+
+
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
+
+
 def cpu_baseline(xr, xi, gr, gi, budget_s: float = 2.0):
     """Time the CPU oracle (FP64 factorised transform, OpenMP over rows) on
     the same step: forward of x and adjoint of g over all rows, repeated
@@ -98,6 +132,17 @@ def cpu_baseline(xr, xi, gr, gi, budget_s: float = 2.0):
         if dt >= budget_s:
             break
     nbytes = 2 * 16 * N * rows * reps
+    # single thread, on a quarter of the rows
+    sub = rows // 4
+    t0 = time.perf_counter()
+    oracle.split_fft(a[:sub], b[:sub], 1)
+    oracle.split_fft(d[:sub], c[:sub], 1)
+    dt1 = time.perf_counter() - t0
+    # the direct definition (O1, O(N^2)) on 64 sampled rows, all threads
+    idx = np.random.default_rng(0).choice(rows, 64, replace=False)
+    t0 = time.perf_counter()
+    oracle.dft_direct(a[idx], b[idx])
+    dto1 = time.perf_counter() - t0
     return {
         "value": round(nbytes / dt / 1e9, 3),
         "unit": "GB/s",
@@ -105,6 +150,13 @@ def cpu_baseline(xr, xi, gr, gi, budget_s: float = 2.0):
         "kind": "oracle",
         "sample": "all %d rows (N=%d), FP64 factorised forward + adjoint, %d repetitions in %.2f s wall"
                   % (rows, N, reps, dt),
+        "host_cpu": host_cpu_model(),
+        "os_cpu_count": os.cpu_count(),
+        "single_thread": {"value": round(2 * 16 * N * sub / dt1 / 1e9, 3), "unit": "GB/s",
+                          "sample": "%d rows forward + adjoint, one thread, %.2f s" % (sub, dt1)},
+        "direct_o1": {"value": round(16 * N * 64 / dto1 / 1e9, 4), "unit": "GB/s",
+                      "sample": "64 sampled rows, FP64 direct evaluation of eq. (5), %d threads, %.2f s"
+                                % (threads, dto1)},
     }
 
 
@@ -386,7 +438,7 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
         },
-        "device": torch.cuda.get_device_name(dev),
+        "device": device_info(dev),
     }
     del sets
     torch.cuda.empty_cache()
