@@ -230,6 +230,48 @@ def mfma_vs_fp32(steps: int = 50, sets: int = 4):
     return out
 
 
+def copy_ceiling(steps: int = 50, sets: int = 4):
+    """A plain device copy of the headline kernel's bytes (128 MiB read and
+    128 MiB written per launch), as the achievable ceiling: torch's copy_ and
+    the HIP runtime's device-to-device memcpy, mean of HIP-event pairs."""
+    import ctypes
+
+    import torch
+
+    dev = torch.device("cuda", 0)
+    src = [torch.randn(2 * N * BATCH, device=dev) for _ in range(sets)]
+    dst = [torch.empty_like(src[0]) for _ in range(sets)]
+    nbytes = src[0].numel() * 4
+    stream = torch.cuda.current_stream(dev)
+    out = {"bytes_each_way": nbytes}
+
+    def timed(fn):
+        for k in range(5):
+            fn(k)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for k in range(steps):
+            ev[k][0].record(stream)
+            fn(k)
+            ev[k][1].record(stream)
+        torch.cuda.synchronize()
+        us = sum(a.elapsed_time(b) for a, b in ev) / steps * 1e3
+        return {"us": round(us, 2), "GBps": round(2 * nbytes / us / 1e3, 1)}
+
+    out["torch_copy"] = timed(lambda k: dst[k % sets].copy_(src[k % sets]))
+    try:
+        hip = ctypes.CDLL("libamdhip64.so", mode=ctypes.RTLD_GLOBAL)
+        hip.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
+                                       ctypes.c_void_p]
+        hip.hipMemcpyAsync.restype = ctypes.c_int
+        d2d = 3  # hipMemcpyDeviceToDevice
+        s = stream.cuda_stream
+        out["hip_memcpy_d2d"] = timed(lambda k: hip.hipMemcpyAsync(dst[k % sets].data_ptr(), src[k % sets].data_ptr(),
+                                                                   nbytes, d2d, s))
+    except OSError:
+        out["hip_memcpy_d2d"] = None
+    return out
+
+
 def dif_n1024(steps: int = 50, sets: int = 4):
     """Forward N=1024 x 16384 through the decimation-in-frequency schedule
     (eq. 9), same inputs as the headline: mean launch time from HIP events."""
@@ -446,6 +488,8 @@ def main():
         out["mfma_vs_fp32"] = mfma_vs_fp32()
         torch.cuda.empty_cache()
     if not args.no_extra:
+        out["copy_ceiling"] = copy_ceiling()
+        torch.cuda.empty_cache()
         out["dif_n1024"] = dif_n1024()
         torch.cuda.empty_cache()
         out["grad_n4096"] = grad_n4096()

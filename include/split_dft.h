@@ -23,8 +23,9 @@
  * Layout: each plane is a contiguous row-major [batch][N] array of float.
  *
  * Ownership: all data pointers are device memory owned by the caller.  A plan
- * owns its device twiddle table (allocated by split_dft_plan, freed by
- * split_dft_destroy).
+ * owns its device tables (twiddles; matrix-core constants) and, for two-pass
+ * lengths, a workspace: allocated by split_dft_plan, freed by
+ * split_dft_destroy.
  *
  * Errors: every entry point returns a status and never aborts or throws.
  * Arguments are validated before any HIP call; on a validation failure no
@@ -34,7 +35,8 @@
  * recent failure on the calling thread.
  *
  * Threads and streams: a plan is immutable after creation; exec and adjoint
- * may run concurrently on different streams with the same plan.
+ * may run concurrently on different streams with the same plan, except on a
+ * two-pass plan through its own workspace (see split_dft_exec_ws).
  */
 #ifndef SPLIT_DFT_H
 #define SPLIT_DFT_H
