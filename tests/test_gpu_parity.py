@@ -197,11 +197,16 @@ def test_adjoint_full_size_n4096():
 
 
 # ------------------------------------------------------- boundary behaviour on the device
-def test_in_place_and_swapped_planes():
-    n, batch = 1024, 37
+# small batches (one block per workgroup) and batches that give every
+# resident workgroup of a persistent schedule several blocks
+@pytest.mark.parametrize("n,batch,dif", [(1024, 37, False), (1024, 16387, False), (64, 262147, False),
+                                         (8192, 2051, False), (1024, 16387, True), (16384, 1027, True)])
+def test_in_place_and_swapped_planes(n, batch, dif):
     xr, xi = inputs.draw_planes(n, batch, "normal", 7)
-    mr, mi = oracle.split_fft_f32(xr.numpy(), xi.numpy())
-    with Plan(n, batch) as p:
+    mirror = oracle.split_fft_dif_f32 if dif else oracle.split_fft_f32
+    mr, mi = mirror(xr.numpy(), xi.numpy())
+    with Plan(n, batch, binding.DIF if dif else 0) as p:
+        say("  in place n=%d batch=%d %s" % (n, batch, p.describe()))
         ar, ai = xr.cuda(), xi.cuda()
         p.exec(ar, ai, ar, ai)
         torch.cuda.synchronize()
