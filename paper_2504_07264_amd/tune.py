@@ -77,26 +77,28 @@ def _time(fn, iters: int, warmup: int = 3) -> float:
     return t[len(t) // 2] * 1e3
 
 
-def schedules(n: int):
-    """Flag values of every compiled FP32 schedule for length n."""
+def schedules(n: int, dif: bool = False):
+    """Flag values of every compiled FP32 schedule for length n (of the
+    decimation-in-frequency factorisation when dif)."""
+    base = binding.DIF if dif else 0
     out = []
     k = 0
     while True:
         try:
-            with Plan(n, 1, variant_flag(k)):
+            with Plan(n, 1, base | variant_flag(k)):
                 pass
         except SplitDFTError:
             return out
-        out.append(variant_flag(k))
+        out.append(base | variant_flag(k))
         k += 1
 
 
-def tune_length(n: int, batch: int, iters: int = 20, sets: int = 3):
+def tune_length(n: int, batch: int, iters: int = 20, sets: int = 3, dif: bool = False):
     """Time every compiled schedule for (n, batch); returns (best flags, timings)."""
     dev = torch.device("cuda", torch.cuda.current_device())
     bufs = [tuple(torch.randn(batch, n, device=dev) for _ in range(4)) for _ in range(sets)]
     timings = {}
-    for flags in schedules(n):
+    for flags in schedules(n, dif):
         with Plan(n, batch, flags) as p:
             us = _time(lambda k: p.exec(*bufs[k % sets]), iters)
             timings[flags] = {"us": round(us, 2), "schedule": p.describe()}
@@ -149,14 +151,14 @@ def lookup(key: str, path=None):
     return None if entry is None else int(entry["flags"])
 
 
-def length_key(n: int, batch: int) -> str:
-    return "length:%d:%d" % (n, batch)
+def length_key(n: int, batch: int, dif: bool = False) -> str:
+    return "%s:%d:%d" % ("length-dif" if dif else "length", n, batch)
 
 
-def tuned_plan(n: int, batch: int, path=None) -> Plan:
+def tuned_plan(n: int, batch: int, path=None, dif: bool = False) -> Plan:
     """A plan with the cached fastest schedule (default schedule if untuned)."""
-    flags = lookup(length_key(n, batch), path)
-    return Plan(n, batch, 0 if flags is None else flags)
+    flags = lookup(length_key(n, batch, dif), path)
+    return Plan(n, batch, (binding.DIF if dif else 0) if flags is None else flags)
 
 
 def tuned_many_plan(lengths, path=None) -> ManyPlan:
@@ -171,13 +173,16 @@ def main(argv=None):
     ap.add_argument("--ragged", type=int, default=0, help="also tune the ragged workload of this many transforms")
     ap.add_argument("--cache", default=None)
     ap.add_argument("--iters", type=int, default=20)
+    ap.add_argument("--dif", action="store_true", help="tune the decimation-in-frequency schedules")
     args = ap.parse_args(argv)
     for n in [int(x) for x in args.lengths.split(",") if x]:
         batch = max(1, args.points // n)
-        best, t = tune_length(n, batch, args.iters)
-        record(length_key(n, batch), best, t, args.cache)
-        print(json.dumps({"n": n, "batch": batch, "best_flags": best, "best": t[best], "candidates": len(t)}),
-              flush=True)
+        if args.dif and not schedules(n, True):
+            continue
+        best, t = tune_length(n, batch, args.iters, dif=args.dif)
+        record(length_key(n, batch, args.dif), best, t, args.cache)
+        print(json.dumps({"n": n, "batch": batch, "dif": args.dif, "best_flags": best, "best": t[best],
+                          "candidates": len(t)}), flush=True)
     if args.ragged:
         from . import inputs
 

@@ -25,6 +25,21 @@ def test_tune_length_and_use_it(tmp_path):
     assert np.array_equal(yr.cpu().numpy(), mr) and np.array_equal(yi.cpu().numpy(), mi)
 
 
+def test_tune_dif_length_and_use_it(tmp_path):
+    path = str(tmp_path / "tune.json")
+    n, batch = 4096, 129
+    best, timings = tune.tune_length(n, batch, iters=3, dif=True)
+    assert best in tune.schedules(n, True) and len(timings) == len(tune.schedules(n, True))
+    tune.record(tune.length_key(n, batch, True), best, timings, path)
+    xr, xi = inputs.draw_planes(n, batch, "normal", 22)
+    with tune.tuned_plan(n, batch, path, dif=True) as p:
+        assert p.describe().startswith("dif ")
+        yr, yi = p.exec(xr.cuda(), xi.cuda())
+        torch.cuda.synchronize()
+    mr, mi = oracle.split_fft_dif_f32(xr.numpy(), xi.numpy())
+    assert np.array_equal(yr.cpu().numpy(), mr) and np.array_equal(yi.cpu().numpy(), mi)
+
+
 def test_tune_many_small(tmp_path):
     path = str(tmp_path / "tune.json")
     lengths = [16, 1 << 14, 256, 1 << 16, 64, 4096] * 3

@@ -17,4 +17,5 @@ def test_cache_round_trip(tmp_path, monkeypatch):
 
 def test_keys_are_stable():
     assert tune.length_key(1024, 16384) == "length:1024:16384"
+    assert tune.length_key(1024, 16384, dif=True) == "length-dif:1024:16384"
     assert tune.ragged_key([16, 32]) == tune.ragged_key([16, 32]) != tune.ragged_key([32, 16])
