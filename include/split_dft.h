@@ -136,7 +136,7 @@ split_dft_status split_dft_destroy(split_dft_plan_t plan);
 
 /* Workspace bytes a plan needs beyond inputs and outputs: 0 for lengths
  * handled in a single pass; for two-pass plans (n >= 2^15 by default) the
- * intermediate of one chunk of transforms, both planes (at most 128 MiB or one
+ * intermediate of one chunk of transforms, both planes (at most 256 MiB or one
  * transform).  0 for a NULL or destroyed plan. */
 size_t split_dft_workspace_bytes(split_dft_plan_t plan);
 
@@ -190,7 +190,7 @@ typedef struct split_dft_graph_s *split_dft_graph_t;
  * Allocates the device-side item list, offsets and twiddle table, and a
  * workspace: with SPLIT_DFT_MANY_ONE_KERNEL and some length >= 2^14, 512 KiB
  * per persistent workgroup; by default, when some length is 2^15 or more, one
- * two-pass chunk (at most 128 MiB). */
+ * two-pass chunk (at most 256 MiB). */
 #define SPLIT_DFT_MANY_ONE_KERNEL (1u << 24)
 split_dft_status split_dft_many_plan(split_dft_many_t *out, const int64_t *lengths, int64_t count,
                                      uint32_t flags);

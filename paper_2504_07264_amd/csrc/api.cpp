@@ -40,8 +40,11 @@ thread_local std::string g_last_error;
 // passes on most devices.  Lengths up to 2^14 run in a single pass.
 constexpr int kTwoPassDefaultLog2N = 15;
 // Workspace per two-pass chunk (both planes); measured on MI355X, chunks of
-// 128 MiB beat smaller ones (fewer, larger launches).
-constexpr int64_t kTwoPassChunkBytes = int64_t{128} << 20;
+// 256 MiB beat smaller ones (fewer, larger launches: 85.3 / 88.0 µs per 2^24
+// points at 2^15 / 2^16 against 88.6 / 91.8 µs with 128 MiB, for batches of
+// 2^25 points and more) and larger ones (the intermediate outgrows the
+// memory-side cache).
+constexpr int64_t kTwoPassChunkBytes = int64_t{256} << 20;
 
 std::mutex g_plans_mu;
 std::unordered_set<const split_dft_plan_s*>& live_plans()

@@ -381,7 +381,11 @@ split_dft_status split_dft_many_plan(split_dft_many_t* out, const int64_t* lengt
         } else if (two && c2 > 0) {
             g.two = &two[0];
             const int64_t n = int64_t{1} << h.m;
-            g.chunk = std::max<int64_t>(1, std::min<int64_t>(g.count, kManyChunkBytes / (n * 2 * 4)));
+            int64_t chunk_bytes = kManyChunkBytes;
+            if (const char* cb = std::getenv("SPLIT_DFT_CHUNK_MIB"))  // tuning override
+                if (std::atoll(cb) > 0)
+                    chunk_bytes = std::atoll(cb) << 20;
+            g.chunk = std::max<int64_t>(1, std::min<int64_t>(g.count, chunk_bytes / (n * 2 * 4)));
             const int64_t nchunks = (g.count + g.chunk - 1) / g.chunk;
             g.chunk = (g.count + nchunks - 1) / nchunks;  // equal chunks
             ws2 = std::max(ws2, static_cast<size_t>(g.chunk) * static_cast<size_t>(n) * 2 * sizeof(float));

@@ -486,15 +486,24 @@ split_fft_pf_kernel(const float* xr, const float* xi, float* yr, float* yi, cons
 
     v4f pr[E / 4], pi[E / 4];
     int64_t blk = blockIdx.x;
+    // With one transform per workgroup the offsets of the next two blocks are
+    // carried (uniform values), so that an offset read from `rows` has arrived
+    // by the time the prefetch needs it.
+    int64_t ahead[2] = {0, 0};
     if (blk < blocks) {
         const int valid = group_valid(blk);
         const int64_t base = group_base(blk);
         load_rows<C, GT>(pr, xr, base, valid, gtid);
         load_rows<C, GT>(pi, xi, base, valid, gtid);
+        if constexpr (TPW == 1) {
+            ahead[0] = base;
+            if (blk + gridDim.x < blocks)
+                ahead[1] = group_base(blk + gridDim.x);
+        }
     }
     for (; blk < blocks; blk += gridDim.x) {
         const int valid = group_valid(blk);
-        const int64_t base = group_base(blk);
+        const int64_t base = TPW == 1 ? ahead[0] : group_base(blk);
         // the position and twiddle addresses below depend only on t; an
         // opaque copy per iteration keeps the compiler from hoisting all of
         // them out of the loop into registers that the prefetch needs
@@ -528,9 +537,13 @@ split_fft_pf_kernel(const float* xr, const float* xi, float* yr, float* yi, cons
         const int64_t nblk = blk + gridDim.x;
         if (nblk < blocks) {
             const int nvalid = group_valid(nblk);
-            const int64_t nbase = group_base(nblk);
+            const int64_t nbase = TPW == 1 ? ahead[1] : group_base(nblk);
             load_rows<C, GT>(pr, xr, nbase, nvalid, gtid);
             load_rows<C, GT>(pi, xi, nbase, nvalid, gtid);
+        }
+        if constexpr (TPW == 1) {
+            ahead[0] = ahead[1];
+            ahead[1] = nblk + gridDim.x < blocks ? group_base(nblk + gridDim.x) : 0;
         }
 
         run_stages<C>(vr, vi, lr, li, t, tw, reinterpret_cast<const float2*>(lds_tw4));
@@ -691,9 +704,9 @@ const Variant kV12[] = {V<12, 4, 1, Y, Y, 2, 4, 2>(),    V<12, 5, 2, Y, Y, 2, 2>
                         V<12, 5, 2, Y, Y, Y, 2>(),       V<12, 5, 1, Y, Y, 2, 2, 2>(), V<12, 4, 2, Y, Y, 2, 4, 2>()};
 const Variant kV13[] = {V<13, 5, 1, Y, Y, 2, 2, 2>(),    V<13, 4, 1, Y, Y, 2, 4, 2>(), V<13, 4, 1, Y, Y, 2, 4, 2, Y>(),
                         V<13, 5, 1, Y, Y, 2, 4, 2>(),    V<13, 5, 1, _, Y, _, 1>()};
-const Variant kV14[] = {V<14, 4, 1, Y, Y, 2, 1, 2, Y>(), V<14, 4, 1, Y, Y, 3, 1, 2, Y>(), V<14, 5, 1, Y, Y, 2, 2, 2, Y>(),
-                        V<14, 4, 1, Y, Y, 2, 1, 2>(),    V<14, 5, 1, Y, Y, 3, 4, 2>(),    V<14, 5, 1, Y, Y, 3, 2, 2>(),
-                        V<14, 5, 1, Y, Y, 2, 2, 2>()};
+const Variant kV14[] = {V<14, 4, 1, Y, Y, 2, 1, 1, Y>(), V<14, 4, 1, Y, Y, 2, 1, 2, Y>(), V<14, 4, 1, Y, Y, 3, 1, 2, Y>(),
+                        V<14, 5, 1, Y, Y, 2, 2, 2, Y>(), V<14, 4, 1, Y, Y, 2, 1, 2>(),    V<14, 5, 1, Y, Y, 3, 4, 2>(),
+                        V<14, 5, 1, Y, Y, 3, 2, 2>(),    V<14, 5, 1, Y, Y, 2, 2, 2>()};
 const Variant kV15[] = {V<15, 5, 1, Y, Y, 3, 1, 2>(), V<15, 5, 1, Y, Y, _, 1>()};
 
 struct VariantList {
