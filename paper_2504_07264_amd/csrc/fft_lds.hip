@@ -702,8 +702,8 @@ const Variant kV11[] = {V<11, 4, 2, Y, Y, 2, 4, 2>(),    V<11, 4, 1, Y, Y, 2, 4,
                         V<11, 4, 2, Y, Y, 2, 4, 2, Y>(), V<11, 4, 2, Y, Y, 2, 4>(),       V<11, 5, 4, Y, Y, Y, 1>()};
 const Variant kV12[] = {V<12, 4, 1, Y, Y, 2, 4, 2>(),    V<12, 5, 2, Y, Y, 2, 2>(),    V<12, 4, 1, Y, Y, 2, 3, 2, Y>(),
                         V<12, 5, 2, Y, Y, Y, 2>(),       V<12, 5, 1, Y, Y, 2, 2, 2>(), V<12, 4, 2, Y, Y, 2, 4, 2>()};
-const Variant kV13[] = {V<13, 5, 1, Y, Y, 2, 2, 2>(),    V<13, 4, 1, Y, Y, 2, 4, 2>(), V<13, 4, 1, Y, Y, 2, 4, 2, Y>(),
-                        V<13, 5, 1, Y, Y, 2, 4, 2>(),    V<13, 5, 1, _, Y, _, 1>()};
+const Variant kV13[] = {V<13, 5, 1, Y, Y, 0, 2, 2>(),    V<13, 5, 1, Y, Y, 2, 2, 2>(), V<13, 4, 1, Y, Y, 2, 4, 2>(),
+                        V<13, 4, 1, Y, Y, 2, 4, 2, Y>(), V<13, 5, 1, Y, Y, 2, 4, 2>(), V<13, 5, 1, _, Y, _, 1>()};
 const Variant kV14[] = {V<14, 4, 1, Y, Y, 2, 1, 1, Y>(), V<14, 4, 1, Y, Y, 2, 1, 2, Y>(), V<14, 4, 1, Y, Y, 3, 1, 2, Y>(),
                         V<14, 5, 1, Y, Y, 2, 2, 2, Y>(), V<14, 4, 1, Y, Y, 2, 1, 2>(),    V<14, 5, 1, Y, Y, 3, 4, 2>(),
                         V<14, 5, 1, Y, Y, 3, 2, 2>(),    V<14, 5, 1, Y, Y, 2, 2, 2>()};
