@@ -10,10 +10,11 @@ so the 256 MB Infinity Cache cannot serve repeats.
 Prints ONE JSON line (rank 0):
   value      algorithmic GB/s of the step (16 B per complex point per
              direction: 8 B read + 8 B written, FP32 planar)
-  roofline   the dominant kernel (the forward length-1024 kernel): algorithmic
-             bytes per launch / its mean launch time from HIP events recorded
-             on the launch stream around every fourth forward launch of the
-             timed region, against 8 TB/s
+  roofline   the dominant kernel (the length-1024 kernel, which both the
+             forward and the adjoint launch): algorithmic bytes per launch /
+             its mean time per launch, from HIP events recorded on the launch
+             stream at both ends of the timed region (which holds nothing
+             else), against 8 TB/s
   cpu_baseline  the CPU oracle (FP64 factorised transform, OpenMP over rows)
              on the same step, timed on this host's cores
 """
@@ -36,7 +37,6 @@ HBM_PEAK_GBS = 8000.0
 N, BATCH = 1024, 16384
 ROTATE_SETS = 4
 PREWARM_S = 1.0
-EVENT_EVERY = 4
 
 # HBM traffic of the forward length-1024 kernel: rocprofv3 FETCH_SIZE and
 # WRITE_SIZE per dispatch, scaled by what the same counters read for a plain
@@ -407,13 +407,9 @@ def main():
     plan = Plan(N, BATCH)
     stream = torch.cuda.current_stream(dev)
 
-    def step(k, ev=None):
+    def step(k):
         s = sets[k % ROTATE_SETS]
-        if ev is not None:
-            ev[0].record(stream)
         plan.exec(s["xr"], s["xi"], s["yr"], s["yi"])
-        if ev is not None:
-            ev[1].record(stream)
         plan.adjoint(s["gr"], s["gi"], s["hr"], s["hi"])
 
     # Untimed: the GPU raises its clocks over the first few hundred
@@ -430,25 +426,28 @@ def main():
         step(k)
     torch.cuda.synchronize()
 
-    # An event pair costs the stream a few microseconds of idle time, so only
-    # every EVENT_EVERY-th forward launch of the timed region is bracketed.
-    sampled = list(range(0, args.steps, EVENT_EVERY))
-    events = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for k in sampled}
+    # The timed region holds only the kernel's launches (forward and adjoint
+    # run the same kernel); one event pair on the launch stream at its two
+    # ends gives the mean time per launch (an event pair around each launch
+    # would idle the stream between launches and add its dispatch time).
+    e_start, e_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    e_start.record(stream)
     for k in range(args.steps):
-        step(k, events.get(k))
+        step(k)
+    e_end.record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
 
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    fwd_ms = sorted(a.elapsed_time(b) for a, b in events.values())
-    fwd_mean_ms = sum(fwd_ms) / len(fwd_ms)
+    launches = 2 * args.steps
+    launch_ms = e_start.elapsed_time(e_end) / launches
     step_bytes = 2 * 16 * N * BATCH
     launch_bytes = 16 * N * BATCH
     gbs = step_bytes / (ms_per_step * 1e-3) / 1e9
     flops = 2 * 5 * N * math.log2(N) * BATCH
-    achieved = launch_bytes / (fwd_mean_ms * 1e-3) / 1e9
+    achieved = launch_bytes / (launch_ms * 1e-3) / 1e9
     traffic = measured_traffic()
 
     out = {
@@ -473,10 +472,8 @@ def main():
             "rotating_buffer_sets": ROTATE_SETS,
         },
         "gflops_5nlogn": round(flops / (ms_per_step * 1e-3) / 1e9, 1),
-        "forward_kernel_us": {"mean": round(fwd_mean_ms * 1e3, 2), "median": round(fwd_ms[len(fwd_ms) // 2] * 1e3, 2),
-                              "p10": round(fwd_ms[len(fwd_ms) // 10] * 1e3, 2),
-                              "p90": round(fwd_ms[(9 * len(fwd_ms)) // 10] * 1e3, 2),
-                              "launches_timed": len(fwd_ms), "every": EVENT_EVERY},
+        "kernel_us_per_launch": {"mean": round(launch_ms * 1e3, 2), "launches": launches,
+                                 "from": "HIP events at both ends of the timed region, launch stream"},
         "roofline": {
             "bound": "hbm",
             "achieved": round(achieved, 1),
