@@ -143,6 +143,46 @@ def test_ragged_workload_20000():
         graph.close()
 
 
+@pytest.mark.parametrize("one_kernel", [False, True])
+def test_offsets_beyond_int32(one_kernel):
+    # more than 2^31 floats per plane, and transforms of every length placed
+    # past element 2^31: offsets and addresses must be formed in 64 bits on
+    # every route (per-length launches, the persistent kernel's items)
+    rng = np.random.default_rng(21)
+    head = np.full((1 << 15) + 1, 1 << 16, dtype=np.int64)
+    tail = np.repeat(1 << np.arange(2, 17), 2)
+    rng.shuffle(tail)
+    lengths = np.concatenate([head, tail])
+    flags = binding.MANY_ONE_KERNEL if one_kernel else 0
+    with ManyPlan(lengths, flags=flags) as p:
+        offs = p.offsets
+        total = p.points
+        assert total > (1 << 31)
+        say("  ragged beyond int32: %d transforms, %d points, one_kernel=%s" % (len(lengths), total, one_kernel))
+        g = torch.Generator(device="cuda")
+        g.manual_seed(23)
+        xr = torch.randn(total, device="cuda", generator=g)
+        xi = torch.randn(total, device="cuda", generator=g)
+        yr, yi = p.exec(xr, xi)
+        torch.cuda.synchronize()
+        edge = int(np.searchsorted(offs, 1 << 31, side="right")) - 1
+        which = sorted({0, edge - 1, edge, edge + 1} | set(range(len(head), len(lengths))))
+        segs = lambda t: {k: to_np_seg(t, offs[k], int(lengths[k])) for k in which}
+        sx_r, sx_i, sy_r, sy_i = segs(xr), segs(xi), segs(yr), segs(yi)
+        bad = []
+        for k in which:
+            mr, mi = oracle.split_fft_f32(sx_r[k][None], sx_i[k][None])
+            if not (np.array_equal(sy_r[k], mr[0]) and np.array_equal(sy_i[k], mi[0])):
+                bad.append((k, int(lengths[k])))
+        assert not bad, "transforms differ from the mirror: %s" % bad[:5]
+        del xr, xi, yr, yi
+    torch.cuda.empty_cache()
+
+
+def to_np_seg(t, off, n):
+    return t[int(off):int(off) + n].cpu().numpy()
+
+
 def test_rejects_bad_lengths_and_pointers():
     for bad in ([4, 3], [1], [1 << 17], [0]):
         with pytest.raises(SplitDFTError) as e:

@@ -259,6 +259,31 @@ def test_batch_one_and_large_batch_small_n():
         assert_bit_exact(yr, yi, mr, mi)
 
 
+@pytest.mark.parametrize("n,batch", [(16, (1 << 27) + 5), (1024, (1 << 21) + 3), (4096, (1 << 19) + 1),
+                                     (1 << 14, (1 << 17) + 1), (1 << 16, (1 << 15) + 1)])
+def test_element_offsets_beyond_int32(n, batch):
+    # more than 2^31 floats per plane: every address of the schedules must be
+    # formed in 64 bits; in place, with sampled rows (including the ones that
+    # straddle element 2^31 and the last one) checked bit-exact
+    points = n * batch
+    assert points > (1 << 31)
+    say("  beyond int32: n=%d batch=%d points=%d" % (n, batch, points))
+    g = torch.Generator(device="cuda")
+    g.manual_seed(17)
+    xr = torch.randn(batch, n, device="cuda", generator=g)
+    xi = torch.randn(batch, n, device="cuda", generator=g)
+    edge = (1 << 31) // n
+    rows = sorted({0, 1, edge - 1, edge, min(edge + 1, batch - 1), batch // 3, batch - 2, batch - 1})
+    sr, si = to_np(xr[rows]), to_np(xi[rows])
+    with Plan(n, batch) as p:
+        p.exec(xr, xi, xr, xi)
+        torch.cuda.synchronize()
+    mr, mi = oracle.split_fft_f32(sr, si)
+    assert_bit_exact(to_np(xr[rows]), to_np(xi[rows]), mr, mi)
+    del xr, xi
+    torch.cuda.empty_cache()
+
+
 def test_two_pass_chunks_and_caller_workspace():
     # more rows than one workspace chunk, in place, then with a caller workspace
     n, batch = 1 << 16, 515
