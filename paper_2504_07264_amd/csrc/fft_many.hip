@@ -194,13 +194,13 @@ __device__ __noinline__ void many_large(Planes pl, int64_t off, float* ws, const
     float* wr = ws + static_cast<int64_t>(blockIdx.x) * (2 * kManyMaxN);
     float* wi = wr + kManyMaxN;
     for (int tile = 0; tile < P1::TILES; ++tile) {
-        tile_process<P1>(xr, xi, wr, wi, tw, tile * P1::C, lds, tid);
+        tile_process<P1>(xr, xi, wr, wi, tw, TileCols<false>{tile * P1::C}, lds, tid);
         __syncthreads();
     }
     // the workgroup's own workspace stores are visible to its loads after the
     // barrier above
     for (int tile = 0; tile < P2::TILES; ++tile) {
-        tile_process<P2>(wr, wi, yr, yi, tw, tile * P2::C, lds, tid);
+        tile_process<P2>(wr, wi, yr, yi, tw, TileCols<false>{tile * P2::C}, lds, tid);
         __syncthreads();
     }
 }

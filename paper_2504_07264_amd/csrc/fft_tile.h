@@ -38,6 +38,7 @@ struct TileCfg {
     static constexpr int TILES = GROUPS / C;                               // per transform
     static constexpr int R2 = 1 << (M - A);  // rows of a pass-2 column (blocks of pass 1)
     static_assert(C % 4 == 0 && E >= 4 && GROUPS % C == 0, "tile shape");
+    static_assert(M <= 16, "32-bit offsets within a transform");
     static_assert(WSC == 0 || (WSC % 4 == 0 && (1 << A) % WSC == 0 && (PASS == 1 || WSC == C)),
                   "tiled workspace: pass 2's tile width");
 };
@@ -53,40 +54,74 @@ __device__ __forceinline__ int tile_lds_row(int r)
         return r;
 }
 
-// Row r of the tile (C contiguous floats) in the source of the pass.
-template <class TC>
-__device__ __forceinline__ int64_t tile_row_offset(int r, int col0)
+// The columns of one tile.  Tile column i is column (col0 - rot + i) mod
+// GROUPS of the pass: rotating the windows by the data's offset from a
+// 128-byte line (rot floats, a multiple of 4) makes every data-side row
+// segment of a tile start on a line, wherever the transform sits.  The tiled
+// workspace stores block position p at p' = (p + sp) mod 2^A, with sp the
+// rotation of pass 2, so that a pass-2 tile still reads one contiguous run.
+// TileCols<false> is the unrotated case (rot = sp = 0 known at compile time,
+// which keeps the column arithmetic foldable into scalar bases).
+template <bool ROT>
+struct TileCols {
+    static constexpr bool ROTATES = true;
+    int col0;  // C x tile index
+    int rot;   // rotation of this pass's columns
+    int sp;    // rotation of block positions in the tiled workspace
+};
+template <>
+struct TileCols<false> {
+    static constexpr bool ROTATES = false;
+    static constexpr int rot = 0, sp = 0;
+    int col0;
+};
+
+template <class TC, class CS>
+__device__ __forceinline__ int tile_col(const CS& tc, int i)
+{
+    if constexpr (CS::ROTATES)
+        return (tc.col0 - tc.rot + i) & (TC::GROUPS - 1);
+    else
+        return tc.col0 + i;
+}
+
+// Tile row r, tile columns i .. i+3 (i a multiple of 4) in the source of the
+// pass (offsets within one transform are below N <= 2^16, so 32-bit offsets
+// from the uniform plane pointer suffice).
+template <class TC, class CS>
+__device__ __forceinline__ int tile_src_offset(int r, int i, const CS& tc)
 {
     if constexpr (TC::PASS == 1)
-        return static_cast<int64_t>(r) * (TC::N >> TC::A) + col0;  // x row r, blocks col0..
+        return r * (TC::N >> TC::A) + tile_col<TC, CS>(tc, i);  // x row r
     else if constexpr (TC::WSC > 0)
-        return static_cast<int64_t>(col0) * TC::R + r * TC::C;      // tiled: one contiguous run
+        return tc.col0 * TC::R + r * TC::C + i;  // tiled: one contiguous run
     else
-        return col0 + (static_cast<int64_t>(r) << TC::A);           // workspace row r, columns col0..
+        return tile_col<TC, CS>(tc, i) + (r << TC::A);  // workspace row r
 }
 
 // tile_in in two steps, so that both planes' loads can be in flight at once:
 // this thread's 16-byte vectors of one plane of the tile ...
-template <class TC>
-__device__ __forceinline__ void tile_load(v4f (&r)[TC::E / 4], const float* src, int col0, int tid)
+// Vector c of a thread covers tile row tid / C4 + c * THREADS / C4 and tile
+// columns 4 * (tid % C4) .. + 3 (THREADS is a multiple of C4 = C / 4).
+template <class TC, class CS>
+__device__ __forceinline__ void tile_load(v4f (&r)[TC::E / 4], const float* src, const CS& tc, int tid)
 {
-    constexpr int C4 = TC::C / 4;
+    constexpr int C4 = TC::C / 4, RSTEP = TC::THREADS / C4;
+    const int c4 = tid % C4, r0 = tid / C4;
 #pragma unroll
-    for (int c = 0; c < TC::E / 4; ++c) {
-        const int f4 = tid + c * TC::THREADS;
-        r[c] = load4<TC::PASS == 1>(src + tile_row_offset<TC>(f4 / C4, col0) + 4 * (f4 % C4));
-    }
+    for (int c = 0; c < TC::E / 4; ++c)
+        r[c] = load4<TC::PASS == 1>(src + tile_src_offset<TC, CS>(r0 + c * RSTEP, 4 * c4, tc));
 }
 
 // ... and into the LDS slots (layout of tile_in).
 template <class TC>
 __device__ __forceinline__ void tile_put(const v4f (&r)[TC::E / 4], float* lds, int tid)
 {
-    constexpr int C4 = TC::C / 4;
+    constexpr int C4 = TC::C / 4, RSTEP = TC::THREADS / C4;
+    const int c4 = tid % C4, r0 = tid / C4;
 #pragma unroll
     for (int c = 0; c < TC::E / 4; ++c) {
-        const int f4 = tid + c * TC::THREADS;
-        const int row = tile_lds_row<TC>(f4 / C4), c4 = f4 % C4;
+        const int row = tile_lds_row<TC>(r0 + c * RSTEP);
 #pragma unroll
         for (int e = 0; e < 4; ++e)
             lds[(4 * c4 + e) * TC::SLOT + lds_index(row)] = r[c][e];
@@ -95,15 +130,15 @@ __device__ __forceinline__ void tile_put(const v4f (&r)[TC::E / 4], float* lds, 
 
 // Tile (R rows x C columns, one plane) into LDS: column i in slot i, row r at
 // lds_index(r) of the slot.
-template <class TC>
-__device__ __forceinline__ void tile_in(const float* src, float* lds, int col0, int tid)
+template <class TC, class CS>
+__device__ __forceinline__ void tile_in(const float* src, float* lds, const CS& tc, int tid)
 {
-    constexpr int C4 = TC::C / 4;
+    constexpr int C4 = TC::C / 4, RSTEP = TC::THREADS / C4;
+    const int c4 = tid % C4, r0 = tid / C4;
 #pragma unroll
     for (int c = 0; c < TC::E / 4; ++c) {
-        const int f4 = tid + c * TC::THREADS;
-        const int r = f4 / C4, c4 = f4 % C4;
-        const v4f v = load4<TC::PASS == 1>(src + tile_row_offset<TC>(r, col0) + 4 * c4);
+        const int r = r0 + c * RSTEP;
+        const v4f v = load4<TC::PASS == 1>(src + tile_src_offset<TC, CS>(r, 4 * c4, tc));
         const int row = tile_lds_row<TC>(r);
 #pragma unroll
         for (int e = 0; e < 4; ++e)
@@ -112,21 +147,26 @@ __device__ __forceinline__ void tile_in(const float* src, float* lds, int col0, 
 }
 
 // Pass 1 output: block c of group i is contiguous in the workspace.
-template <class TC>
-__device__ __forceinline__ void blocks_out(float* dst, const float* lds, int col0, int tid)
+template <class TC, class CS>
+__device__ __forceinline__ void blocks_out(float* dst, const float* lds, const CS& tc, int tid)
 {
     if constexpr (TC::WSC > 0) {
-        // tiled workspace: for each group of WSC positions, the tile's C
-        // blocks (input columns col0 + i) form one run of C x WSC floats
+        // tiled workspace: for each group of WSC stored positions p', the
+        // tile's C blocks (input columns tile_col(i)) form runs of WSC floats
+        // at consecutive columns (one run of C x WSC floats unless the
+        // tile's columns wrap around)
         constexpr int W4 = TC::WSC / 4;
+        constexpr int PM = (1 << TC::A) - 1;
+        constexpr bool LINEAR = TC::THREADS % (W4 * TC::C) == 0;  // i, p4w fixed per thread
 #pragma unroll
         for (int c = 0; c < TC::E / 4; ++c) {
             const int f4 = tid + c * TC::THREADS;
-            const int p4w = f4 % W4, rest = f4 / W4;
-            const int i = rest % TC::C, pg = rest / TC::C;
-            const float* s = lds + i * TC::SLOT + lds_index(pg * TC::WSC + 4 * p4w);
-            *reinterpret_cast<v4f*>(dst + static_cast<int64_t>(pg) * (TC::R2 * TC::WSC) +
-                                    static_cast<int64_t>(col0 + i) * TC::WSC + 4 * p4w) =
+            const int p4w = (LINEAR ? tid : f4) % W4, rest = (LINEAR ? tid : f4) / W4;
+            const int i = rest % TC::C;
+            const int pg = LINEAR ? rest / TC::C + c * (TC::THREADS / (W4 * TC::C)) : rest / TC::C;
+            const int p = (pg * TC::WSC + 4 * p4w - tc.sp) & PM;
+            const float* s = lds + i * TC::SLOT + lds_index(p);
+            *reinterpret_cast<v4f*>(dst + (pg * (TC::R2 * TC::WSC) + tile_col<TC, CS>(tc, i) * TC::WSC + 4 * p4w)) =
                 v4f{s[0], s[1], s[2], s[3]};
         }
         return;
@@ -137,24 +177,24 @@ __device__ __forceinline__ void blocks_out(float* dst, const float* lds, int col
         const int f4 = tid + c * TC::THREADS;
         const int i = f4 / R4, p4 = f4 % R4;
         const float* s = lds + i * TC::SLOT + lds_index(4 * p4);
-        const int blk = rev_bits(col0 + i, TC::M - TC::A);
-        *reinterpret_cast<v4f*>(dst + static_cast<int64_t>(blk) * TC::R + 4 * p4) = v4f{s[0], s[1], s[2], s[3]};
+        const int blk = rev_bits(tile_col<TC, CS>(tc, i), TC::M - TC::A);
+        *reinterpret_cast<v4f*>(dst + (blk * TC::R + 4 * p4)) = v4f{s[0], s[1], s[2], s[3]};
     }
 }
 
 // Pass 2 output: natural positions lo + (p << A), along tile rows.
-template <class TC>
-__device__ __forceinline__ void rows_out(float* dst, const float* lds, int col0, int tid)
+template <class TC, class CS>
+__device__ __forceinline__ void rows_out(float* dst, const float* lds, const CS& tc, int tid)
 {
-    constexpr int C4 = TC::C / 4;
+    constexpr int C4 = TC::C / 4, RSTEP = TC::THREADS / C4;
+    const int c4 = tid % C4, r0 = tid / C4;
+    // the output is in natural order whatever the workspace layout
+    const int col = tile_col<TC, CS>(tc, 4 * c4);
 #pragma unroll
     for (int c = 0; c < TC::E / 4; ++c) {
-        const int f4 = tid + c * TC::THREADS;
-        const int r = f4 / C4, c4 = f4 % C4;
+        const int r = r0 + c * RSTEP;
         const float* s = lds + (4 * c4) * TC::SLOT + lds_index(r);
-        // the output is in natural order whatever the workspace layout
-        store4<true>(dst + col0 + (static_cast<int64_t>(r) << TC::A) + 4 * c4,
-                     v4f{s[0], s[TC::SLOT], s[2 * TC::SLOT], s[3 * TC::SLOT]});
+        store4<true>(dst + (col + (r << TC::A)), v4f{s[0], s[TC::SLOT], s[2 * TC::SLOT], s[3 * TC::SLOT]});
     }
 }
 
@@ -181,12 +221,12 @@ __device__ __forceinline__ void regs_tile(const float (&v)[TC::E], float* slot, 
         slot[lds_index(position<TC::LT, Last::S, Last::RP>(t, u))] = v[u];
 }
 
-// One tile of a pass: the C groups (columns) col0 .. col0 + C - 1 of the
+// One tile of a pass: the C groups (columns) tile_col(tc, 0 .. C - 1) of the
 // transform whose planes start at xr, xi (source) and yr, yi (destination).
 // lds holds LDS_WORDS floats; every thread of the workgroup takes part.
-template <class TC>
+template <class TC, class CS>
 __device__ __forceinline__ void tile_process(const float* xr, const float* xi, float* yr, float* yi,
-                                             const float2* __restrict__ tw, int col0, float* lds, int tid)
+                                             const float2* __restrict__ tw, const CS& tc, float* lds, int tid)
 {
     constexpr int E = TC::E, LT = TC::LT, T = TC::T, C = TC::C;
     const int g = TC::GF ? tid % C : tid >> LT;  // group (column) within the tile
@@ -199,8 +239,8 @@ __device__ __forceinline__ void tile_process(const float* xr, const float* xi, f
     if constexpr (TC::SPLIT) {
         // both planes' loads in flight at once; LDS holds one plane at a time
         v4f pr[E / 4], pi[E / 4];
-        tile_load<TC>(pr, xr, col0, tid);
-        tile_load<TC>(pi, xi, col0, tid);
+        tile_load<TC, CS>(pr, xr, tc, tid);
+        tile_load<TC, CS>(pi, xi, tc, tid);
         tile_put<TC>(pr, lds, tid);
         __syncthreads();
         tile_regs<TC>(vr, lr, t);
@@ -209,8 +249,8 @@ __device__ __forceinline__ void tile_process(const float* xr, const float* xi, f
         __syncthreads();
         tile_regs<TC>(vi, lr, t);
     } else {
-        tile_in<TC>(xr, lds, col0, tid);
-        tile_in<TC>(xi, area_i, col0, tid);
+        tile_in<TC, CS>(xr, lds, tc, tid);
+        tile_in<TC, CS>(xi, area_i, tc, tid);
         __syncthreads();
         tile_regs<TC>(vr, lr, t);
         tile_regs<TC>(vi, li, t);
@@ -218,7 +258,7 @@ __device__ __forceinline__ void tile_process(const float* xr, const float* xi, f
     // the group's exchanges reuse its slot
     __syncthreads();
 
-    const int lo_g = TC::PASS == 1 ? 0 : col0 + g;
+    const int lo_g = TC::PASS == 1 ? 0 : tile_col<TC, CS>(tc, g);
     stages<E, LT, 0, Pass<TC::MA, TC::RB, 0>::RP, TwTable<0>, TC::TW_SHIFT>(vr, vi, t, tw, lo_g);
     if constexpr (TC::NP > 1)
         later_passes<TC::MA, TC::RB, 1, TC::SPLIT, E, TwTable<0>, TC::TW_SHIFT, TC::GF ? 1024 : T>(vr, vi, lr, li, t, tw,
@@ -229,26 +269,26 @@ __device__ __forceinline__ void tile_process(const float* xr, const float* xi, f
         regs_tile<TC>(vr, lr, t);
         __syncthreads();
         if constexpr (TC::PASS == 1)
-            blocks_out<TC>(yr, lds, col0, tid);
+            blocks_out<TC, CS>(yr, lds, tc, tid);
         else
-            rows_out<TC>(yr, lds, col0, tid);
+            rows_out<TC, CS>(yr, lds, tc, tid);
         __syncthreads();
         regs_tile<TC>(vi, lr, t);
         __syncthreads();
         if constexpr (TC::PASS == 1)
-            blocks_out<TC>(yi, lds, col0, tid);
+            blocks_out<TC, CS>(yi, lds, tc, tid);
         else
-            rows_out<TC>(yi, lds, col0, tid);
+            rows_out<TC, CS>(yi, lds, tc, tid);
     } else {
         regs_tile<TC>(vr, lr, t);
         regs_tile<TC>(vi, li, t);
         __syncthreads();
         if constexpr (TC::PASS == 1) {
-            blocks_out<TC>(yr, lds, col0, tid);
-            blocks_out<TC>(yi, area_i, col0, tid);
+            blocks_out<TC, CS>(yr, lds, tc, tid);
+            blocks_out<TC, CS>(yi, area_i, tc, tid);
         } else {
-            rows_out<TC>(yr, lds, col0, tid);
-            rows_out<TC>(yi, area_i, col0, tid);
+            rows_out<TC, CS>(yr, lds, tc, tid);
+            rows_out<TC, CS>(yi, area_i, tc, tid);
         }
     }
 }

@@ -42,13 +42,17 @@ struct TwoPass {
     int lds1, lds2;          // LDS bytes
     bool gf2;                // pass 2 lanes run over columns first
     // rows: NULL for contiguous transforms, else the element offset of each
-    // transform in the data arrays (the workspace side is always contiguous)
+    // transform in the data arrays (the workspace side is always contiguous);
+    // out_line: line_offset(yr) of pass 2's output plane, in both calls
     hipError_t (*pass1)(const float* xr, const float* xi, float* wr, float* wi, const float2* tw, int64_t batch,
-                        const int64_t* rows, hipStream_t stream);
+                        const int64_t* rows, int out_line, hipStream_t stream);
     hipError_t (*pass2)(const float* wr, const float* wi, float* yr, float* yi, const float2* tw, int64_t batch,
-                        const int64_t* rows, hipStream_t stream);
+                        const int64_t* rows, int out_line, hipStream_t stream);
     bool wst;  // workspace in pass-2 tile order (else natural position order)
 };
+
+// Offset in floats, modulo 32, of a plane pointer from a 128-byte line.
+inline int line_offset(const float* p) { return static_cast<int>((reinterpret_cast<uintptr_t>(p) >> 2) & 31); }
 
 // Compiled two-pass schedules for length 2^m (count returned through *count).
 const TwoPass* two_pass_for(int m, int* count);
