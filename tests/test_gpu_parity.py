@@ -284,6 +284,50 @@ def test_element_offsets_beyond_int32(n, batch):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("m", [14, 15, 16])
+def test_two_pass_planes_off_cache_lines(m):
+    # planes that start 16 bytes off a 128-byte line, each by a different
+    # amount (input and output real planes differ, so pass 1's and pass 2's
+    # tile rotations differ): the rotated tiles must give the same bits
+    n, batch = 1 << m, 37
+    xr, xi = inputs.draw_planes(n, batch, "normal", 19)
+    mr, mi = oracle.split_fft_f32(xr.numpy(), xi.numpy())
+    flags = variant_flag(len(list_single_pass(m))) if m == 14 else 0  # the two-pass schedule at 2^14
+    say("  two-pass off-line planes n=%d batch=%d" % (n, batch))
+    pool = torch.zeros(4 * (n * batch + 64), device="cuda")
+    stride = n * batch + 64
+
+    def plane(k, off):
+        return pool[k * stride + off: k * stride + off + n * batch].view(batch, n)
+
+    ar, ai, yr, yi = plane(0, 4), plane(1, 28), plane(2, 16), plane(3, 8)
+    ar.copy_(xr.cuda())
+    ai.copy_(xi.cuda())
+    with Plan(n, batch, flags) as p:
+        assert p.describe().startswith("two-pass")
+        p.exec(ar, ai, yr, yi)
+        torch.cuda.synchronize()
+        assert_bit_exact(to_np(yr), to_np(yi), mr, mi)
+        # and in place, from the same off-line planes
+        p.exec(ar, ai, ar, ai)
+        torch.cuda.synchronize()
+        assert_bit_exact(to_np(ar), to_np(ai), mr, mi)
+
+
+def list_single_pass(m):
+    out, k = [], 0
+    while True:
+        try:
+            with Plan(1 << m, 1, variant_flag(k)) as p:
+                d = p.describe()
+        except SplitDFTError:
+            return out
+        if d.startswith("two-pass"):
+            return out
+        out.append(d)
+        k += 1
+
+
 def test_two_pass_chunks_and_caller_workspace():
     # more rows than one workspace chunk, in place, then with a caller workspace
     n, batch = 1 << 16, 515
