@@ -154,10 +154,9 @@ split_dft_status run(split_dft_plan_t p, const float* xr, const float* xi, float
         for (int64_t s0 = 0; s0 < p->batch; s0 += p->chunk) {
             const int64_t k = p->batch - s0 < p->chunk ? p->batch - s0 : p->chunk;
             const int64_t off = s0 * p->n;
-            const int out_line = splitdft::line_offset(yr + off);
-            hipError_t e = p->two->pass1(xr + off, xi + off, wr, wi, p->d_tw, k, nullptr, out_line, st);
+            hipError_t e = p->two->pass1(xr + off, xi + off, wr, wi, p->d_tw, k, nullptr, st);
             if (e == hipSuccess)
-                e = p->two->pass2(wr, wi, yr + off, yi + off, p->d_tw, k, nullptr, out_line, st);
+                e = p->two->pass2(wr, wi, yr + off, yi + off, p->d_tw, k, nullptr, st);
             if (e != hipSuccess)
                 return fail_hip(e, "two-pass kernel launch");
         }

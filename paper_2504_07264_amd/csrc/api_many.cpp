@@ -190,10 +190,9 @@ split_dft_status many_launch(split_dft_many_t p, const float* xr, const float* x
                 float* wi = p->d_ws + g.chunk * (int64_t{1} << g.m);
                 for (int64_t s0 = 0; s0 < g.count && e == hipSuccess; s0 += g.chunk) {
                     const int64_t c = g.count - s0 < g.chunk ? g.count - s0 : g.chunk;
-                    const int out_line = splitdft::line_offset(a.out_r[k]);
-                    e = g.two->pass1(a.in_r[k], a.in_i[k], wr, wi, p->d_tw, c, g.d_rows + s0, out_line, stream);
+                    e = g.two->pass1(a.in_r[k], a.in_i[k], wr, wi, p->d_tw, c, g.d_rows + s0, stream);
                     if (e == hipSuccess)
-                        e = g.two->pass2(wr, wi, a.out_r[k], a.out_i[k], p->d_tw, c, g.d_rows + s0, out_line, stream);
+                        e = g.two->pass2(wr, wi, a.out_r[k], a.out_i[k], p->d_tw, c, g.d_rows + s0, stream);
                 }
             }
             if (e != hipSuccess) {

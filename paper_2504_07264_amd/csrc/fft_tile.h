@@ -55,30 +55,30 @@ __device__ __forceinline__ int tile_lds_row(int r)
 }
 
 // The columns of one tile.  Tile column i is column (col0 - rot + i) mod
-// GROUPS of the pass: rotating the windows by the data's offset from a
-// 128-byte line (rot floats, a multiple of 4) makes every data-side row
-// segment of a tile start on a line, wherever the transform sits.  The tiled
-// workspace stores block position p at p' = (p + sp) mod 2^A, with sp the
-// rotation of pass 2, so that a pass-2 tile still reads one contiguous run.
-// TileCols<false> is the unrotated case (rot = sp = 0 known at compile time,
-// which keeps the column arithmetic foldable into scalar bases).
+// GROUPS of the pass.  Pass 1 reads its rows of C floats straight from the
+// data; rotating the windows by the data's offset from a 128-byte line (rot
+// floats, a multiple of 4) makes each of those segments start on a line,
+// wherever the transform sits.  (Pass 2 is not rotated: its data side is
+// the stores, which lose little to a misaligned start, and its rotated build
+// needs more registers than that gains.)  TileCols<false> is the unrotated
+// case, with rot = 0 known at compile time.
 template <bool ROT>
 struct TileCols {
     static constexpr bool ROTATES = true;
     int col0;  // C x tile index
-    int rot;   // rotation of this pass's columns
-    int sp;    // rotation of block positions in the tiled workspace
+    int rot;   // rotation of the columns
 };
 template <>
 struct TileCols<false> {
     static constexpr bool ROTATES = false;
-    static constexpr int rot = 0, sp = 0;
+    static constexpr int rot = 0;
     int col0;
 };
 
 template <class TC, class CS>
 __device__ __forceinline__ int tile_col(const CS& tc, int i)
 {
+    static_assert(TC::PASS == 1 || !CS::ROTATES, "only pass 1 rotates its columns");
     if constexpr (CS::ROTATES)
         return (tc.col0 - tc.rot + i) & (TC::GROUPS - 1);
     else
@@ -151,12 +151,11 @@ template <class TC, class CS>
 __device__ __forceinline__ void blocks_out(float* dst, const float* lds, const CS& tc, int tid)
 {
     if constexpr (TC::WSC > 0) {
-        // tiled workspace: for each group of WSC stored positions p', the
-        // tile's C blocks (input columns tile_col(i)) form runs of WSC floats
-        // at consecutive columns (one run of C x WSC floats unless the
-        // tile's columns wrap around)
+        // tiled workspace: for each group of WSC positions, the tile's C
+        // blocks (input columns tile_col(i)) form runs of WSC floats at
+        // consecutive columns (one run of C x WSC floats unless the tile's
+        // columns wrap around)
         constexpr int W4 = TC::WSC / 4;
-        constexpr int PM = (1 << TC::A) - 1;
         constexpr bool LINEAR = TC::THREADS % (W4 * TC::C) == 0;  // i, p4w fixed per thread
 #pragma unroll
         for (int c = 0; c < TC::E / 4; ++c) {
@@ -164,8 +163,7 @@ __device__ __forceinline__ void blocks_out(float* dst, const float* lds, const C
             const int p4w = (LINEAR ? tid : f4) % W4, rest = (LINEAR ? tid : f4) / W4;
             const int i = rest % TC::C;
             const int pg = LINEAR ? rest / TC::C + c * (TC::THREADS / (W4 * TC::C)) : rest / TC::C;
-            const int p = (pg * TC::WSC + 4 * p4w - tc.sp) & PM;
-            const float* s = lds + i * TC::SLOT + lds_index(p);
+            const float* s = lds + i * TC::SLOT + lds_index(pg * TC::WSC + 4 * p4w);
             *reinterpret_cast<v4f*>(dst + (pg * (TC::R2 * TC::WSC) + tile_col<TC, CS>(tc, i) * TC::WSC + 4 * p4w)) =
                 v4f{s[0], s[1], s[2], s[3]};
         }

@@ -15,8 +15,9 @@
 // (see TileCfg), so that pass 1 writes and pass 2 reads long contiguous runs
 // and only the inherently strided sides (pass 1's gather of each block, pass
 // 2's natural-order output) use 128-byte segments.  When a transform's data
-// does not start on a 128-byte line (ragged batches), its tiles take their
-// columns rotated so that those segments start on lines again (TileCols).
+// does not start on a 128-byte line (ragged batches), its pass-1 tiles take
+// their columns rotated so that the read segments start on lines again
+// (TileCols).
 //
 // A workgroup handles a tile of C groups (columns) x R = 2^MA rows.  The tile
 // is loaded and stored with 16-byte vectors along rows (C contiguous floats)
@@ -33,15 +34,13 @@
 namespace splitdft {
 namespace {
 
-// out_line: the offset in floats, modulo 32, of the transforms' final output
-// plane (yr of pass 2) from a 128-byte line, so that both passes agree on the
-// rotation of pass 2's columns (which sets the workspace order).
-// ROT: rotate the tile columns (ragged transforms, or planes off a 128-byte
-// line); the unrotated build serves aligned batches.
+// ROT (pass 1 only): rotate the tile columns by the data's offset from a
+// 128-byte line (ragged transforms, or planes off a line); the unrotated build
+// serves the rest.
 template <class TC, bool ROT>
 __global__ void __launch_bounds__(TC::THREADS)
 split_fft_tile_kernel(const float* xr, const float* xi, float* yr, float* yi, const float2* __restrict__ tw,
-                      int tiles_per_transform, const int64_t* __restrict__ rows, int out_line)
+                      int tiles_per_transform, const int64_t* __restrict__ rows)
 {
     __shared__ float lds[TC::LDS_WORDS];
     const int64_t t = blockIdx.x / tiles_per_transform;
@@ -52,11 +51,8 @@ split_fft_tile_kernel(const float* xr, const float* xi, float* yr, float* yi, co
     const int64_t obase = TC::PASS == 1 ? wbase : dbase;
     const int col0 = (blockIdx.x % tiles_per_transform) * TC::C;
     if constexpr (ROT) {
-        // rotations (floats from a 128-byte line) of pass 1's data reads and
-        // of pass 2's data writes for this transform
-        const int out_rot = static_cast<int>((out_line + dbase) & 31);
-        const int in_rot = static_cast<int>(((reinterpret_cast<uintptr_t>(xr) >> 2) + dbase) & 31);
-        const TileCols<true> tc{col0, TC::PASS == 1 ? in_rot : out_rot, out_rot};
+        const int rot = static_cast<int>(((reinterpret_cast<uintptr_t>(xr) >> 2) + dbase) & 31);
+        const TileCols<true> tc{col0, rot};
         tile_process<TC>(xr + ibase, xi + ibase, yr + obase, yi + obase, tw, tc, lds, threadIdx.x);
     } else {
         const TileCols<false> tc{col0};
@@ -66,21 +62,22 @@ split_fft_tile_kernel(const float* xr, const float* xi, float* yr, float* yi, co
 
 template <class TC>
 hipError_t launch_tile(const float* xr, const float* xi, float* yr, float* yi, const float2* tw, int64_t batch,
-                       const int64_t* rows, int out_line, hipStream_t stream)
+                       const int64_t* rows, hipStream_t stream)
 {
     const int64_t blocks = batch * TC::TILES;
     if (blocks > INT_MAX)
         return hipErrorInvalidConfiguration;
-    // contiguous transforms (N a multiple of 32) share the planes' own line
-    // offsets; the unrotated build needs both to be zero
-    const int in_line = line_offset(xr);
-    const bool rot = rows != nullptr || (out_line & 31) != 0 || (TC::PASS == 1 && in_line != 0);
-    if (rot)
-        hipLaunchKernelGGL((split_fft_tile_kernel<TC, true>), dim3(static_cast<unsigned>(blocks)), dim3(TC::THREADS),
-                           0, stream, xr, xi, yr, yi, tw, TC::TILES, rows, out_line & 31);
-    else
-        hipLaunchKernelGGL((split_fft_tile_kernel<TC, false>), dim3(static_cast<unsigned>(blocks)), dim3(TC::THREADS),
-                           0, stream, xr, xi, yr, yi, tw, TC::TILES, rows, 0);
+    // contiguous transforms (N a multiple of 32) share the plane's own line
+    // offset, so the unrotated build serves them when it is zero
+    if constexpr (TC::PASS == 1) {
+        if (rows != nullptr || line_offset(xr) != 0) {
+            hipLaunchKernelGGL((split_fft_tile_kernel<TC, true>), dim3(static_cast<unsigned>(blocks)),
+                               dim3(TC::THREADS), 0, stream, xr, xi, yr, yi, tw, TC::TILES, rows);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((split_fft_tile_kernel<TC, false>), dim3(static_cast<unsigned>(blocks)), dim3(TC::THREADS), 0,
+                       stream, xr, xi, yr, yi, tw, TC::TILES, rows);
     return hipGetLastError();
 }
 

@@ -42,12 +42,11 @@ struct TwoPass {
     int lds1, lds2;          // LDS bytes
     bool gf2;                // pass 2 lanes run over columns first
     // rows: NULL for contiguous transforms, else the element offset of each
-    // transform in the data arrays (the workspace side is always contiguous);
-    // out_line: line_offset(yr) of pass 2's output plane, in both calls
+    // transform in the data arrays (the workspace side is always contiguous)
     hipError_t (*pass1)(const float* xr, const float* xi, float* wr, float* wi, const float2* tw, int64_t batch,
-                        const int64_t* rows, int out_line, hipStream_t stream);
+                        const int64_t* rows, hipStream_t stream);
     hipError_t (*pass2)(const float* wr, const float* wi, float* yr, float* yi, const float2* tw, int64_t batch,
-                        const int64_t* rows, int out_line, hipStream_t stream);
+                        const int64_t* rows, hipStream_t stream);
     bool wst;  // workspace in pass-2 tile order (else natural position order)
 };
 

@@ -287,8 +287,8 @@ def test_element_offsets_beyond_int32(n, batch):
 @pytest.mark.parametrize("m", [14, 15, 16])
 def test_two_pass_planes_off_cache_lines(m):
     # planes that start 16 bytes off a 128-byte line, each by a different
-    # amount (input and output real planes differ, so pass 1's and pass 2's
-    # tile rotations differ): the rotated tiles must give the same bits
+    # amount (pass 1 rotates its tiles by the input's offset; the output and
+    # imaginary planes sit elsewhere): the rotated tiles must give the same bits
     n, batch = 1 << m, 37
     xr, xi = inputs.draw_planes(n, batch, "normal", 19)
     mr, mi = oracle.split_fft_f32(xr.numpy(), xi.numpy())
