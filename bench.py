@@ -301,6 +301,38 @@ def dif_n1024(steps: int = 50, sets: int = 4):
                 "GBps": round(16 * w.n * w.batch / us / 1e3, 1), "schedule": plan.describe()}
 
 
+def two_pass_large(reps: int = 20):
+    """Forward N=2^15 x 512 and N=2^16 x 256 (2^24 points each, the two-pass
+    schedule): mean time per launch from events around back-to-back execs."""
+    import torch
+
+    from paper_2504_07264_amd import Plan, inputs
+
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    res = {}
+    for m in (15, 16):
+        n, batch = 1 << m, (1 << 24) >> m
+        xr, xi = inputs.draw_planes(n, batch, "normal", 30 + m)
+        x = (xr.to(dev), xi.to(dev))
+        y = (torch.empty(batch, n, device=dev), torch.empty(batch, n, device=dev))
+        with Plan(n, batch) as plan:
+            for _ in range(3):
+                plan.exec(x[0], x[1], y[0], y[1])
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                plan.exec(x[0], x[1], y[0], y[1])
+            e1.record(stream)
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) / reps * 1e3
+            res["n%d_b%d" % (n, batch)] = {"us": round(us, 2), "GBps": round(16 * n * batch / us / 1e3, 1),
+                                          "schedule": plan.describe()}
+        del x, y
+    res["note"] = "forward only; GB/s counts 16 B per point, the two passes move twice that"
+    return res
+
+
 def grad_n4096(steps: int = 30, sets: int = 3):
     """Forward + adjoint (the autograd step's two kernels) at N=4096 x 4096."""
     import torch
@@ -495,6 +527,8 @@ def main():
         out["dif_n1024"] = dif_n1024()
         torch.cuda.empty_cache()
         out["grad_n4096"] = grad_n4096()
+        torch.cuda.empty_cache()
+        out["two_pass_large"] = two_pass_large()
         torch.cuda.empty_cache()
         out["ragged_grouped"] = ragged_grouped()
         torch.cuda.empty_cache()
