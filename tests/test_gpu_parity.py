@@ -328,6 +328,43 @@ def list_single_pass(m):
         k += 1
 
 
+@pytest.mark.parametrize("n,batch", [(1024, 4099), (4096, 515), (1 << 16, 600)])
+def test_captured_in_a_graph(n, batch):
+    # exec and adjoint captured in a torch (HIP) graph: single-pass persistent,
+    # one-block-per-workgroup and chunked two-pass schedules launch nothing but
+    # kernels, so every replay must equal the eager result, with other work and
+    # synchronisations between the replays
+    xr, xi = inputs.draw_planes(n, batch, "normal", 27)
+    say("  graph capture n=%d batch=%d" % (n, batch))
+    with Plan(n, batch) as p:
+        ar, ai = xr.cuda(), xi.cuda()
+        er, ei = p.exec(ar, ai)
+        gr, gi = p.adjoint(er, ei)
+        torch.cuda.synchronize()
+        yr, yi = torch.empty_like(ar), torch.empty_like(ai)
+        hr, hi = torch.empty_like(ar), torch.empty_like(ai)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):  # warm-up on the capturing stream
+            p.exec(ar, ai, yr, yi)
+            p.adjoint(yr, yi, hr, hi)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            p.exec(ar, ai, yr, yi)
+            p.adjoint(yr, yi, hr, hi)
+        for k in range(3):
+            for t in (yr, yi, hr, hi):
+                t.fill_(float("nan"))
+            torch.cuda.synchronize()
+            graph.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(yr, er) and torch.equal(yi, ei), "replay %d forward" % k
+            assert torch.equal(hr, gr) and torch.equal(hi, gi), "replay %d adjoint" % k
+        del graph
+
+
 def test_two_pass_chunks_and_caller_workspace():
     # more rows than one workspace chunk, in place, then with a caller workspace
     n, batch = 1 << 16, 515
