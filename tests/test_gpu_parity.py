@@ -365,6 +365,21 @@ def test_captured_in_a_graph(n, batch):
         del graph
 
 
+@pytest.mark.parametrize("n", [16, 1024, 1 << 15])
+def test_subnormal_inputs_bit_exact(n):
+    # inputs in the FP32 subnormal range (and a mix with normal values): the
+    # kernels keep subnormals (no flush to zero), as the oracle's FP32 mirror
+    # does, so the results stay bit-identical
+    xr, xi = inputs.draw_planes(n, 9, "normal", 29)
+    tiny = 2.0 ** -140
+    xr = xr * tiny
+    xi[1::2] = xi[1::2] * tiny  # odd rows: both planes subnormal; even rows: normal imaginary parts
+    assert (xr.abs() < 2.0 ** -126).all() and (xr != 0).any() and torch.isfinite(xi).all()
+    mr, mi = oracle.split_fft_f32(xr.numpy(), xi.numpy())
+    yr, yi = gpu_exec(n, 9, xr, xi)
+    assert_bit_exact(yr, yi, mr, mi)
+
+
 def test_two_pass_chunks_and_caller_workspace():
     # more rows than one workspace chunk, in place, then with a caller workspace
     n, batch = 1 << 16, 515
