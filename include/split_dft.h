@@ -37,6 +37,17 @@
  * Threads and streams: a plan is immutable after creation; exec and adjoint
  * may run concurrently on different streams with the same plan, except on a
  * two-pass plan through its own workspace (see split_dft_exec_ws).
+ *
+ * Alignment: 16-byte aligned planes are required; planes that start on a
+ * 128-byte line run fastest (torch allocations do).
+ *
+ * Environment (read when a plan is created):
+ *   SPLIT_DFT_LOG=1          print each plan's schedule to stderr;
+ *   SPLIT_DFT_CHUNK_MIB=k    two-pass workspace chunks of at most k MiB
+ *                            instead of 256 (a tuning override);
+ *   SPLIT_DFT_FAIL_ALLOC=1   make plan creation fail with
+ *                            SPLIT_DFT_ERR_OUT_OF_MEMORY (to test callers'
+ *                            error paths).
  */
 #ifndef SPLIT_DFT_H
 #define SPLIT_DFT_H
