@@ -186,8 +186,8 @@ def main(argv=None):
     if args.ragged:
         from . import inputs
 
-        lengths, _ = inputs.ragged_lengths(args.ragged, inputs.RAGGED_KMIN, inputs.RAGGED_KMAX, inputs.RAGGED_SEED)
-        lengths = lengths.tolist()
+        _, lengths = inputs.ragged_lengths(args.ragged, inputs.RAGGED_KMIN, inputs.RAGGED_KMAX, inputs.RAGGED_SEED)
+        lengths = [int(v) for v in lengths.tolist()]
         best, t = tune_many(lengths)
         record(ragged_key(lengths), best, t, args.cache)
         print(json.dumps({"ragged": args.ragged, "best_flags": best, "timings": t}), flush=True)

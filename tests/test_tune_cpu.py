@@ -19,3 +19,22 @@ def test_keys_are_stable():
     assert tune.length_key(1024, 16384) == "length:1024:16384"
     assert tune.length_key(1024, 16384, dif=True) == "length-dif:1024:16384"
     assert tune.ragged_key([16, 32]) == tune.ragged_key([16, 32]) != tune.ragged_key([32, 16])
+
+
+def test_cli_ragged_path_passes_the_workload_lengths(monkeypatch, tmp_path):
+    # the --ragged path hands tune_many the drawn lengths (a list of powers of
+    # two from the workload recipe) and records under their key
+    seen = {}
+
+    def fake_tune_many(lengths):
+        seen["lengths"] = lengths
+        return 0, {0: 1.0}
+
+    monkeypatch.setattr(tune, "tune_many", fake_tune_many)
+    monkeypatch.setattr(tune, "device_key", lambda device=None: "test-device")
+    path = str(tmp_path / "tune.json")
+    tune.main(["--lengths", "", "--ragged", "12", "--cache", path])
+    ls = seen["lengths"]
+    assert isinstance(ls, list) and len(ls) == 12
+    assert all(isinstance(v, int) and v >= 16 and v & (v - 1) == 0 for v in ls)
+    assert tune.lookup(tune.ragged_key(ls), path) == 0
