@@ -13,6 +13,13 @@ import torch
 from .binding import cached_plan
 
 
+def _operand(t: torch.Tensor) -> torch.Tensor:
+    """Contiguous and 16-byte aligned (the library's requirement): a view that
+    starts inside an allocation is copied."""
+    t = t.contiguous()
+    return t if t.data_ptr() % 16 == 0 else t.clone()
+
+
 class SplitDFTFunction(torch.autograd.Function):
     @staticmethod
     def forward(ctx, xr: torch.Tensor, xi: torch.Tensor):
@@ -22,7 +29,7 @@ class SplitDFTFunction(torch.autograd.Function):
         batch = xr.numel() // n
         ctx.meta = (n, batch, xr.device, xr.shape)
         p = cached_plan(n, batch, xr.device)
-        yr, yi = p.exec(xr.contiguous(), xi.contiguous())
+        yr, yi = p.exec(_operand(xr), _operand(xi))
         return yr.view(xr.shape), yi.view(xr.shape)
 
     @staticmethod
@@ -33,7 +40,7 @@ class SplitDFTFunction(torch.autograd.Function):
         if gyi is None:
             gyi = torch.zeros(shape, dtype=torch.float32, device=device)
         p = cached_plan(n, batch, device)
-        gxr, gxi = p.adjoint(gyr.contiguous(), gyi.contiguous())
+        gxr, gxi = p.adjoint(_operand(gyr), _operand(gyi))
         return gxr.view(shape), gxi.view(shape)
 
 

@@ -92,3 +92,27 @@ def test_one_output_used_and_leading_dims():
     hr, hi = oracle.split_adjoint_f32(ones, np.zeros_like(ones))
     assert np.array_equal(ar.grad.reshape(6, n).cpu().numpy(), hr)
     assert np.array_equal(ai.grad.reshape(6, n).cpu().numpy(), hi)
+
+
+def test_views_that_start_off_alignment_and_strided_views():
+    # a view starting 4 bytes into its allocation, and a transposed
+    # (non-contiguous) one: the wrapper copies them to aligned, contiguous
+    # operands; results and gradients equal the mirror's bits
+    n, rows = 64, 10
+    xr, xi = inputs.draw_planes(n, rows, "normal", 33)
+    br = torch.empty(rows * n + 1, device="cuda")
+    br[1:] = xr.reshape(-1).cuda()
+    ar = br[1:].view(rows, n)
+    assert ar.data_ptr() % 16 != 0
+    ai_t = xi.cuda().t().contiguous().t()  # non-contiguous view of the same values
+    assert not ai_t.is_contiguous()
+    ar.requires_grad_(True)
+    ai_t.requires_grad_(True)
+    yr, yi = split_dft_autograd(ar, ai_t)
+    (yr.sum() + 2 * yi.sum()).backward()
+    torch.cuda.synchronize()
+    mr, mi = oracle.split_fft_f32(xr.numpy(), xi.numpy())
+    assert np.array_equal(yr.detach().cpu().numpy(), mr) and np.array_equal(yi.detach().cpu().numpy(), mi)
+    ones = np.ones((rows, n), np.float32)
+    hr, hi = oracle.split_adjoint_f32(ones, 2 * ones)
+    assert np.array_equal(ar.grad.cpu().numpy(), hr) and np.array_equal(ai_t.grad.cpu().numpy(), hi)
