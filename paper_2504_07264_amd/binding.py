@@ -251,13 +251,20 @@ _plan_cache = {}
 _plan_cache_lock = threading.Lock()
 
 
+PLAN_CACHE_SIZE = 8  # most recently used plans kept (each holds device tables, two-pass ones a workspace)
+
+
 def cached_plan(n: int, batch: int, device: torch.device, flags: int = FP32) -> Plan:
+    """A plan for (n, batch, device, flags) from a small most-recently-used
+    cache; an evicted plan is destroyed once nothing references it."""
     key = (int(n), int(batch), str(device), int(flags))
     with _plan_cache_lock:
-        p = _plan_cache.get(key)
+        p = _plan_cache.pop(key, None)
         if p is None:
             p = Plan(n, batch, flags, device)
-            _plan_cache[key] = p
+        _plan_cache[key] = p  # most recent last
+        while len(_plan_cache) > PLAN_CACHE_SIZE:
+            _plan_cache.pop(next(iter(_plan_cache)))
         return p
 
 

@@ -116,3 +116,17 @@ def test_views_that_start_off_alignment_and_strided_views():
     ones = np.ones((rows, n), np.float32)
     hr, hi = oracle.split_adjoint_f32(ones, 2 * ones)
     assert np.array_equal(ar.grad.cpu().numpy(), hr) and np.array_equal(ai_t.grad.cpu().numpy(), hi)
+
+
+def test_cached_plans_are_bounded():
+    # the convenience entry points keep a small most-recently-used set of plans
+    from paper_2504_07264_amd import binding
+
+    n = 16
+    for batch in range(1, binding.PLAN_CACHE_SIZE + 5):
+        xr, xi = inputs.draw_planes(n, batch, "normal", 40 + batch)
+        yr, yi = binding.split_dft(xr.cuda(), xi.cuda())
+        torch.cuda.synchronize()
+        mr, mi = oracle.split_fft_f32(xr.numpy(), xi.numpy())
+        assert np.array_equal(yr.cpu().numpy(), mr) and np.array_equal(yi.cpu().numpy(), mi)
+        assert len(binding._plan_cache) <= binding.PLAN_CACHE_SIZE
