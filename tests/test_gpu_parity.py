@@ -408,6 +408,13 @@ def test_two_pass_chunks_and_caller_workspace():
                                       w.data_ptr(), ws, s) == 0
         torch.cuda.synchronize()
         assert_bit_exact(to_np(yr), to_np(yi), hr, hi)
+        # a NULL workspace means the plan's own
+        yr.zero_()
+        yi.zero_()
+        assert L.split_dft_exec_ws(p.handle, br.data_ptr(), bi.data_ptr(), yr.data_ptr(), yi.data_ptr(),
+                                   None, 0, s) == 0
+        torch.cuda.synchronize()
+        assert_bit_exact(to_np(yr), to_np(yi), mr, mi)
         # too small, misaligned or overlapping workspaces are rejected before any launch
         assert L.split_dft_exec_ws(p.handle, br.data_ptr(), bi.data_ptr(), yr.data_ptr(), yi.data_ptr(),
                                    w.data_ptr(), ws - 16, s) == 2
