@@ -459,3 +459,21 @@ def test_dif_every_length(m):
     ar, ai = gpu_exec(n, batch, xr, xi, binding.DIF, adjoint=True)
     hr, hi = oracle.split_fft_dif_f32(xi.numpy(), xr.numpy())
     assert_bit_exact(ar, ai, hi, hr)
+
+
+def test_plan_info_and_describe():
+    with Plan(1024, 7) as p:
+        info = p.info()
+        assert info == {"n": 1024, "batch": 7, "log2n": 10, "ept": 16, "tpw": 4}
+        assert p.workspace_bytes() == 0 and "persistent" in p.describe()
+    with Plan(1 << 16, 3) as p:
+        info = p.info()
+        assert info["log2n"] == 16 and info["tpw"] == 0
+        assert p.describe().startswith("two-pass") and p.workspace_bytes() == 3 * (1 << 16) * 2 * 4
+    with Plan(256, 5, binding.PRECISIONS["bf16x2"]) as p:
+        assert p.describe().startswith("mfma16x16x32 bf16x2")
+    from paper_2504_07264_amd import ManyPlan
+    with ManyPlan([16, 1 << 15, 64]) as mp:
+        mi = mp.info()
+        assert mi["count"] == 3 and mi["points"] == 16 + (1 << 15) + 64
+        assert mi["workgroups"] > 0 and mi["items"] >= 1 and mi["workspace_bytes"] >= (1 << 15) * 2 * 4
