@@ -36,7 +36,10 @@
  *
  * Threads and streams: a plan is immutable after creation; exec and adjoint
  * may run concurrently on different streams with the same plan, except on a
- * two-pass plan through its own workspace (see split_dft_exec_ws).
+ * two-pass plan through its own workspace (see split_dft_exec_ws).  A plan
+ * runs on the HIP device that was current when it was created; calling exec
+ * or adjoint (or building a graph) with another device current returns
+ * SPLIT_DFT_ERR_INVALID_PLAN.
  *
  * Alignment: 16-byte aligned planes are required; planes that start on a
  * 128-byte line run fastest (torch allocations do).
@@ -44,7 +47,8 @@
  * Environment (read when a plan is created):
  *   SPLIT_DFT_LOG=1          print each plan's schedule to stderr;
  *   SPLIT_DFT_CHUNK_MIB=k    two-pass workspace chunks of at most k MiB
- *                            instead of 256 (a tuning override);
+ *                            (k clamped to 65536) instead of 256 (a
+ *                            tuning override);
  *   SPLIT_DFT_FAIL_ALLOC=1   make plan creation fail with
  *                            SPLIT_DFT_ERR_OUT_OF_MEMORY (to test callers'
  *                            error paths).

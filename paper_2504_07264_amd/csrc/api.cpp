@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -133,6 +134,11 @@ split_dft_status run(split_dft_plan_t p, const float* xr, const float* xi, float
     const split_dft_status vs = validate_io(p, xr, xi, yr, yi);
     if (vs != SPLIT_DFT_OK)
         return vs;
+    // the plan's tables live on the device it was created on
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != p->device)
+        return fail(SPLIT_DFT_ERR_INVALID_PLAN, "the plan belongs to HIP device " + std::to_string(p->device) +
+                                                    ", the current device is " + std::to_string(cur));
     const hipStream_t st = static_cast<hipStream_t>(stream);
     if (p->two) {
         float* w = static_cast<float*>(ws);
@@ -269,9 +275,9 @@ split_dft_status split_dft_plan(split_dft_plan_t* out, int64_t n, int64_t batch,
     float* d_ws = nullptr;
     if (two) {
         int64_t chunk_bytes = kTwoPassChunkBytes;
-        if (const char* cb = std::getenv("SPLIT_DFT_CHUNK_MIB"))  // tuning override
+        if (const char* cb = std::getenv("SPLIT_DFT_CHUNK_MIB"))  // tuning override, 1 MiB .. 64 GiB
             if (std::atoll(cb) > 0)
-                chunk_bytes = std::atoll(cb) << 20;
+                chunk_bytes = std::min<int64_t>(std::atoll(cb), int64_t{1} << 16) << 20;
         chunk = chunk_bytes / (n * 2 * static_cast<int64_t>(sizeof(float)));
         chunk = chunk < 1 ? 1 : (chunk > batch ? batch : chunk);
         // equal chunks: no short launch at the end
@@ -280,6 +286,8 @@ split_dft_status split_dft_plan(split_dft_plan_t* out, int64_t n, int64_t batch,
         ws_bytes = static_cast<size_t>(chunk) * static_cast<size_t>(n) * 2 * sizeof(float);
         e = hipMalloc(&d_ws, ws_bytes);
         if (e != hipSuccess) {
+            if (d_mfma)
+                (void)hipFree(d_mfma);
             (void)hipFree(d_tw);
             return e == hipErrorOutOfMemory ? fail(SPLIT_DFT_ERR_OUT_OF_MEMORY, "hipMalloc of the workspace")
                                             : fail_hip(e, "hipMalloc of the workspace");

@@ -146,6 +146,12 @@ split_dft_status many_launch(split_dft_many_t p, const float* xr, const float* x
         *msg = "grouped plan is NULL, destroyed or not created by split_dft_many_plan";
         return SPLIT_DFT_ERR_INVALID_PLAN;
     }
+    int cur = -1;  // the plan's tables and workspace live on the device it was created on
+    if (hipGetDevice(&cur) != hipSuccess || cur != p->device) {
+        *msg = "the grouped plan belongs to HIP device " + std::to_string(p->device) + ", the current device is " +
+               std::to_string(cur);
+        return SPLIT_DFT_ERR_INVALID_PLAN;
+    }
     const size_t bytes = static_cast<size_t>(p->points) * sizeof(float);
     split_dft_status st = SPLIT_DFT_OK;
     if (fwd && (st = check_dir(p, xr, xi, yr, yi, msg)) != SPLIT_DFT_OK)
@@ -382,9 +388,9 @@ split_dft_status split_dft_many_plan(split_dft_many_t* out, const int64_t* lengt
             g.two = &two[0];
             const int64_t n = int64_t{1} << h.m;
             int64_t chunk_bytes = kManyChunkBytes;
-            if (const char* cb = std::getenv("SPLIT_DFT_CHUNK_MIB"))  // tuning override
+            if (const char* cb = std::getenv("SPLIT_DFT_CHUNK_MIB"))  // tuning override, 1 MiB .. 64 GiB
                 if (std::atoll(cb) > 0)
-                    chunk_bytes = std::atoll(cb) << 20;
+                    chunk_bytes = std::min<int64_t>(std::atoll(cb), int64_t{1} << 16) << 20;
             g.chunk = std::max<int64_t>(1, std::min<int64_t>(g.count, chunk_bytes / (n * 2 * 4)));
             const int64_t nchunks = (g.count + g.chunk - 1) / g.chunk;
             g.chunk = (g.count + nchunks - 1) / nchunks;  // equal chunks
