@@ -59,6 +59,12 @@ struct TwTable {
     {
         return tw[(1 << (level - 1)) - OFF + q];
     }
+    // q = qt + qc with qt and qc on disjoint bits (qt per thread, qc fixed
+    // per register)
+    static __device__ __forceinline__ float2 get2(const float2* __restrict__ tw, int level, int qt, int qc)
+    {
+        return get(tw, level, qt + qc);
+    }
 };
 
 // TwQuarter<MQ>: only the first quarter turn of stage MQ's twiddles,
@@ -77,6 +83,32 @@ struct TwQuarter {
         const bool upper = (idx & H) != 0;
         return make_float2(upper ? 0.0f - w.y : w.x, upper ? w.x : w.y);
     }
+    static __device__ __forceinline__ float2 get2(const float2* __restrict__ tw, int level, int qt, int qc)
+    {
+        return get(tw, level, qt + qc);
+    }
+};
+
+// TwQuarterLds<MQ>: the values of TwQuarter<MQ> from a copy of its table in
+// LDS that holds entry k at slot(k).  Later passes read the table at strides
+// of 2^(MQ - level) entries, which in the plain layout fall into few LDS banks
+// (up to 16 lanes on one bank); slot(k) XORs the higher 5-bit groups of k
+// into its low 5 bits, which spreads any run of 2^s-strided entries over 32
+// consecutive 8-byte slots, i.e. over all banks.  slot() is linear over XOR,
+// so with q = qt + qc on disjoint bits the per-thread part slot(qt ...) is
+// computed once per stage and each register only XORs a constant.
+template <int MQ>
+struct TwQuarterLds {
+    static constexpr int H = 1 << (MQ - 2);
+    static __host__ __device__ constexpr int slot(int k) { return k ^ (((k >> 5) ^ (k >> 10) ^ (k >> 15)) & 31); }
+    static __device__ __forceinline__ float2 get2(const float2* tw, int level, int qt, int qc)
+    {
+        const int it = qt << (MQ - level), ic = qc << (MQ - level);
+        const float2 w = tw[slot(it & (H - 1)) ^ slot(ic & (H - 1))];
+        const bool upper = ((it ^ ic) & H) != 0;
+        return make_float2(upper ? 0.0f - w.y : w.x, upper ? w.x : w.y);
+    }
+    static __device__ __forceinline__ float2 get(const float2* tw, int level, int q) { return get2(tw, level, q, 0); }
 };
 
 // Stages S+1 .. S+RP of a group of 2^MA positions on the E registers of one
@@ -111,9 +143,11 @@ __device__ __forceinline__ void stages(float (&vr)[E], float (&vi)[E], int t, co
                     rotate(ar, ai, w.x, w.y);
                 }
             } else {
-                const int o = t + ((u >> RP) << LT);
-                const int ql = (o & ((1 << S) - 1)) + ((u & (half - 1)) << S);
-                const float2 w = TW::get(tw, A + S + k, lo_g + (ql << A));
+                // ql = (o & (2^S - 1)) + (u mod half) 2^S with o = t + (u >> RP) 2^LT,
+                // split into the thread's part and the register's (t < 2^LT)
+                const int qt = lo_g + ((t & ((1 << S) - 1)) << A);
+                const int qc = ((((u >> RP) << LT) & ((1 << S) - 1)) + ((u & (half - 1)) << S)) << A;
+                const float2 w = TW::get2(tw, A + S + k, qt, qc);
                 rotate(ar, ai, w.x, w.y);
             }
             const float ur = vr[u], ui = vi[u];
@@ -160,9 +194,9 @@ __device__ __forceinline__ void stages_dif(float (&vr)[E], float (&vi)[E], int t
                     rotate(dr, di, w.x, w.y);
                 }
             } else {
-                const int o = t + ((u >> RP) << LT);
-                const int q = (o & ((1 << S) - 1)) + ((u & (half - 1)) << S);
-                const float2 w = TW::get(tws, S + k, q);
+                const int qt = t & ((1 << S) - 1);  // as in stages()
+                const int qc = (((u >> RP) << LT) & ((1 << S) - 1)) + ((u & (half - 1)) << S);
+                const float2 w = TW::get2(tws, S + k, qt, qc);
                 rotate(dr, di, w.x, w.y);
             }
             vr[v] = dr;

@@ -62,8 +62,9 @@ constexpr int kMaxDevices = 64;
 //   NT     nontemporal hints on the streaming global loads and stores
 //   TWL    twiddles of passes >= 1: 0 read from the table in global memory;
 //          staged once per workgroup in LDS: 1 table entries [2^RB, N),
-//          2 the first quarter turn of stage M (TwQuarter); 3 that quarter
-//          turn read from global memory
+//          2 the first quarter turn of stage M, in the bank-spreading slot
+//          order of TwQuarterLds; 3 that quarter turn read from global memory
+//          (TwQuarter)
 //   WPE    minimum waves per SIMD the register allocation must allow (1 = any)
 //   F4IO   global I/O as 16-byte vectors over the workgroup's contiguous
 //          rows, staged through LDS: 0 none, 1 loads and stores, 2 loads only
@@ -100,6 +101,18 @@ struct Cfg {
     static_assert(TWL < 2 || M >= 3, "the quarter-turn table needs N >= 8");
     static_assert(!PF || F4IN, "the prefetching form loads through the 16-byte staging");
 };
+
+// The quarter-turn table of stage M (entries [N/2, N/2 + N/4) of the plan's
+// table) into LDS, entry k at TwQuarterLds slot k; consecutive k of one
+// 32-entry run go to a permutation of that run, so the writes do not collide.
+template <class C>
+__device__ __forceinline__ void stage_quarter(const float2* __restrict__ tw, float2* lds_q, int tid)
+{
+    using Q = TwQuarterLds<(C::M >= 3 ? C::M : 3)>;
+    const float2* src = tw + C::N / 2;
+    for (int k = tid; k < C::TWQ; k += C::THREADS)
+        lds_q[Q::slot(k)] = src[k];
+}
 
 // 16-byte loads of one plane of a sync group's rows (valid floats only) into
 // LDS; float f of the group's block lands in slot f / N at lds_index(f mod N).
@@ -240,7 +253,9 @@ __device__ __forceinline__ void run_stages(float (&vr)[C::E], float (&vi)[C::E],
     constexpr int M = C::M, RB = C::RB, E = C::E, LT = C::LT;
     using TW = typename std::conditional<
         (C::TW_LDS > 0), TwTable<E>,
-        typename std::conditional<(C::TWQ > 0 || C::TWL == 3), TwQuarter<(M >= 3 ? M : 3)>, TwTable<0>>::type>::type;
+        typename std::conditional<
+            (C::TWQ > 0), TwQuarterLds<(M >= 3 ? M : 3)>,
+            typename std::conditional<(C::TWL == 3), TwQuarter<(M >= 3 ? M : 3)>, TwTable<0>>::type>::type>::type;
     const float2* tws = (C::TW_LDS > 0 || C::TWQ > 0) ? lds_tw : (C::TWL == 3 ? tw + C::N / 2 : tw);
     if constexpr (C::DIF) {
         using First = PassD<M, RB, 0>;
@@ -291,9 +306,7 @@ split_fft_lds_kernel(const float* xr, const float* xi, float* yr, float* yi, con
             lds_tw4[k] = src[k];
         __syncthreads();
     } else if constexpr (C::TWQ > 0) {
-        const v4f* src = reinterpret_cast<const v4f*>(tw + N / 2);
-        for (int k = tid; k < C::TWQ / 2; k += C::THREADS)
-            lds_tw4[k] = src[k];
+        stage_quarter<C>(tw, reinterpret_cast<float2*>(lds_tw4), tid);
         __syncthreads();
     }
 
@@ -468,9 +481,7 @@ split_fft_pf_kernel(const float* xr, const float* xi, float* yr, float* yi, cons
             lds_tw4[k] = src[k];
         __syncthreads();
     } else if constexpr (C::TWQ > 0) {
-        const v4f* src = reinterpret_cast<const v4f*>(tw + N / 2);
-        for (int k = tid; k < C::TWQ / 2; k += C::THREADS)
-            lds_tw4[k] = src[k];
+        stage_quarter<C>(tw, reinterpret_cast<float2*>(lds_tw4), tid);
         __syncthreads();
     }
 
@@ -702,7 +713,7 @@ const Variant kV11[] = {V<11, 4, 2, Y, Y, 2, 4, 2>(),    V<11, 4, 1, Y, Y, 2, 4,
                         V<11, 4, 2, Y, Y, 2, 4, 2, Y>(), V<11, 4, 2, Y, Y, 2, 4>(),       V<11, 5, 4, Y, Y, Y, 1>()};
 const Variant kV12[] = {V<12, 4, 1, Y, Y, 2, 4, 2>(),    V<12, 5, 2, Y, Y, 2, 2>(),    V<12, 4, 1, Y, Y, 2, 3, 2, Y>(),
                         V<12, 5, 2, Y, Y, Y, 2>(),       V<12, 5, 1, Y, Y, 2, 2, 2>(), V<12, 4, 2, Y, Y, 2, 4, 2>()};
-const Variant kV13[] = {V<13, 5, 1, Y, Y, 0, 2, 2>(),    V<13, 5, 1, Y, Y, 2, 2, 2>(), V<13, 4, 1, Y, Y, 2, 4, 2>(),
+const Variant kV13[] = {V<13, 4, 1, Y, Y, 2, 4, 2>(),    V<13, 5, 1, Y, Y, 0, 2, 2>(), V<13, 5, 1, Y, Y, 2, 2, 2>(),
                         V<13, 4, 1, Y, Y, 2, 4, 2, Y>(), V<13, 5, 1, Y, Y, 2, 4, 2>(), V<13, 5, 1, _, Y, _, 1>()};
 const Variant kV14[] = {V<14, 4, 1, Y, Y, 2, 1, 1, Y>(), V<14, 4, 1, Y, Y, 2, 1, 2, Y>(), V<14, 4, 1, Y, Y, 3, 1, 2, Y>(),
                         V<14, 5, 1, Y, Y, 2, 2, 2, Y>(), V<14, 4, 1, Y, Y, 2, 1, 2>(),    V<14, 5, 1, Y, Y, 3, 4, 2>(),
