@@ -96,7 +96,9 @@ struct TwQuarter {
 // into its low 5 bits, which spreads any run of 2^s-strided entries over 32
 // consecutive 8-byte slots, i.e. over all banks.  slot() is linear over XOR,
 // so with q = qt + qc on disjoint bits the per-thread part slot(qt ...) is
-// computed once per stage and each register only XORs a constant.
+// computed once per stage and each register only XORs a constant.  slot()
+// keeps bits 5 and up and XORs the low 5 bits with a function of them, so it
+// maps [0, H) onto itself and is its own inverse.
 template <int MQ>
 struct TwQuarterLds {
     static constexpr int H = 1 << (MQ - 2);
@@ -110,6 +112,9 @@ struct TwQuarterLds {
     }
     static __device__ __forceinline__ float2 get(const float2* tw, int level, int q) { return get2(tw, level, q, 0); }
 };
+static_assert(TwQuarterLds<16>::slot(TwQuarterLds<16>::slot(12345)) == 12345 &&
+                  TwQuarterLds<16>::slot(32) == 33 && TwQuarterLds<16>::slot(1024) == 1025,
+              "slot layout of the LDS quarter table");
 
 // Stages S+1 .. S+RP of a group of 2^MA positions on the E registers of one
 // thread.  The group's position p is the transform's position lo_g + (p << A)
