@@ -698,7 +698,7 @@ const Variant kV6[] = {V<6, 4, 64, _, Y, 2, 4, 1, Y>(), V<6, 4, 32, _, Y, 2, 4, 
                        V<6, 3, 32, _, _, _, 1>()};
 const Variant kV7[] = {V<7, 4, 32, Y, Y, 2, 4, 1, Y>(), V<7, 4, 16, _, Y, 2, 4, 1, Y>(), V<7, 4, 16, _, Y, Y, 1, Y>(),
                        V<7, 4, 32, _, _, _, 1>()};
-const Variant kV8[] = {V<8, 4, 16, Y, Y, 2, 4, 1, Y>(), V<8, 4, 16, Y, Y, Y, 4, Y>(), V<8, 4, 32, Y, Y, 2, 4, 1, Y>(),
+const Variant kV8[] = {V<8, 4, 16, Y, Y, Y, 4, Y>(), V<8, 4, 16, Y, Y, 2, 4, 1, Y>(), V<8, 4, 32, Y, Y, 2, 4, 1, Y>(),
                        V<8, 4, 16, _, _, _, 1>()};
 const Variant kV9[] = {V<9, 4, 8, Y, Y, 2, 4, 2, Y>(), V<9, 4, 8, Y, Y, 2, 4, 1, Y>(), V<9, 4, 4, Y, Y, 2, 4, 2, Y>(),
                        V<9, 4, 8, Y, Y, Y, 4, Y>(),    V<9, 4, 8, _, Y, Y, 1>(),       V<9, 4, 8, Y, Y, 2, 4, 2>()};
