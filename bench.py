@@ -408,7 +408,7 @@ def main():
                     help="only launch the forward kernel and a calibration copy (for rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; the transforms are independent per row, "
+        print("bench.py: the benchmark runs on one GPU only; the transforms are independent per row, "
               "so N GPUs would each run the same kernel on batch/N rows with no communication. "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
