@@ -79,11 +79,19 @@ struct Planes {
     float* yi;
 };
 
+// Twiddles of the group items' later passes: the first quarter turn of stage
+// kGroupTwM (the longest group length) in LDS, in TwQuarterLds slot order;
+// omega^(i,q) of every shorter length has an equal-valued entry there.
+constexpr int kGroupTwM = 13;
+using GroupTw = TwQuarterLds<kGroupTwM>;
+constexpr int kGroupTwEntries = 1 << (kGroupTwM - 2);
+
 // Group item: transforms order[first .. first + count) of length 2^M.
 template <int M>
 __device__ __forceinline__ void many_group_body(Planes pl, const int64_t* __restrict__ offsets,
                                                 const int32_t* __restrict__ order, int64_t first, int count,
-                                                const float2* __restrict__ tw, float* lds, int64_t* s_off, int tid)
+                                                const float2* __restrict__ tw, const float2* s_tw, float* lds,
+                                                int64_t* s_off, int tid)
 {
     using G = GroupShape<M>;
     constexpr int E = G::E, LT = G::LT, T = G::T, RB = G::RB, N = G::N;
@@ -148,7 +156,7 @@ __device__ __forceinline__ void many_group_body(Planes pl, const int64_t* __rest
 
     stages<E, LT, 0, Pass<M, RB, 0>::RP>(vr, vi, t, tw);
     if constexpr (G::NP > 1)
-        later_passes<M, RB, 1, true, E, TwQuarter<M>>(vr, vi, lr, lr, t, tw + N / 2);
+        later_passes<M, RB, 1, true, E, GroupTw>(vr, vi, lr, lr, t, s_tw);
 
     using Last = Pass<M, RB, G::NP - 1>;
 #pragma unroll
@@ -177,9 +185,10 @@ __device__ __forceinline__ void many_group_body(Planes pl, const int64_t* __rest
 template <int M, int WPE>
 __device__ __noinline__ void many_group(Planes pl, const int64_t* __restrict__ offsets,
                                         const int32_t* __restrict__ order, int64_t first, int count,
-                                        const float2* __restrict__ tw, float* lds, int64_t* s_off, int tid)
+                                        const float2* __restrict__ tw, const float2* s_tw, float* lds,
+                                        int64_t* s_off, int tid)
 {
-    many_group_body<M>(pl, offsets, order, first, count, tw, lds, s_off, tid);
+    many_group_body<M>(pl, offsets, order, first, count, tw, s_tw, lds, s_off, tid);
 }
 
 // Large item: one transform through this workgroup's workspace region.
@@ -219,7 +228,12 @@ split_fft_many_kernel(const float* in_r0, const float* in_i0, float* out_r0, flo
     __shared__ float lds[LARGE ? kLdsWords : kGroupLdsWords];
     __shared__ int64_t s_off[kMT];
     __shared__ int s_item;
+    __shared__ float2 s_tw[kGroupTwEntries];
     const int tid = threadIdx.x;
+    // stage kGroupTwM's block starts at table entry 2^(kGroupTwM - 1); the
+    // barrier at the top of the item loop orders these writes before any read
+    for (int k = tid; k < kGroupTwEntries; k += kMT)
+        s_tw[GroupTw::slot(k)] = tw[(1 << (kGroupTwM - 1)) + k];
     for (;;) {
         if (tid == 0)
             s_item = atomicAdd(&queue[0], 1);
@@ -238,7 +252,7 @@ split_fft_many_kernel(const float* in_r0, const float* in_i0, float* out_r0, flo
         switch (m) {
 #define SDFT_GROUP(MM)                                                                   \
     case MM:                                                                             \
-        many_group<MM, WPE>(pl, offsets, order, first, count, tw, lds, s_off, tid);      \
+        many_group<MM, WPE>(pl, offsets, order, first, count, tw, s_tw, lds, s_off, tid); \
         break;
             SDFT_GROUP(2)
             SDFT_GROUP(3)
