@@ -143,6 +143,30 @@ def test_ragged_workload_20000():
         graph.close()
 
 
+def test_many_short_transforms():
+    # only lengths 2^4 .. 2^11: everything runs in the persistent kernel, each
+    # workgroup through many group items of every short length
+    lengths, (xr, xi, gr, gi) = inputs.draw_ragged(60000, 4, 11, 5)
+    lengths = lengths.numpy()
+    total = int(lengths.sum())
+    say("  short ragged batch: %d transforms, %d points" % (len(lengths), total))
+    with ManyPlan(lengths) as p:
+        offs = p.offsets
+        dx = [t.cuda() for t in (xr, xi, gr, gi)]
+        out = [torch.empty(total, device="cuda") for _ in range(4)]
+        graph = p.graph(dx[0], dx[1], out[0], out[1], dx[2], dx[3], out[2], out[3])
+        graph.launch()
+        torch.cuda.synchronize()
+        rng = np.random.default_rng(13)
+        which = sorted(set(rng.choice(len(lengths), 300, replace=False).tolist())
+                       | {int(np.flatnonzero(lengths == (1 << k))[-1]) for k in range(4, 12)})
+        o = [t.cpu().numpy() for t in out]
+        check(lengths, offs, o[0], o[1], mirror_ragged(lengths, offs, xr.numpy(), xi.numpy(), which), "forward")
+        check(lengths, offs, o[2], o[3], mirror_ragged(lengths, offs, gr.numpy(), gi.numpy(), which, adjoint=True),
+              "adjoint")
+        graph.close()
+
+
 @pytest.mark.parametrize("one_kernel", [False, True])
 def test_offsets_beyond_int32(one_kernel):
     # more than 2^31 floats per plane, and transforms of every length placed
