@@ -202,7 +202,7 @@ class Plan:
         if not t.is_contiguous():
             raise ValueError("%s must be contiguous" % name)
 
-    def _call(self, fn, ar, ai, out_r, out_i):
+    def _call(self, fn, fn_ws, ar, ai, out_r, out_i, workspace):
         for t, nm in ((ar, "input real"), (ai, "input imag")):
             self._check_plane(t, nm)
         if out_r is None:
@@ -211,8 +211,14 @@ class Plan:
             out_i = torch.empty_like(ai)
         self._check_plane(out_r, "output real")
         self._check_plane(out_i, "output imag")
-        args = (self._h, ar.data_ptr(), ai.data_ptr(), out_r.data_ptr(), out_i.data_ptr(),
-                _stream_handle(self._index))
+        args = (self._h, ar.data_ptr(), ai.data_ptr(), out_r.data_ptr(), out_i.data_ptr())
+        if workspace is not None:
+            if not isinstance(workspace, torch.Tensor) or not workspace.is_cuda \
+                    or workspace.get_device() != self._index or not workspace.is_contiguous():
+                raise ValueError("workspace must be a contiguous tensor on %s" % self.device)
+            fn = fn_ws
+            args = args + (workspace.data_ptr(), workspace.numel() * workspace.element_size())
+        args = args + (_stream_handle(self._index),)
         if torch.cuda.current_device() == self._index:
             check(fn(*args))
         else:
@@ -220,13 +226,17 @@ class Plan:
                 check(fn(*args))
         return out_r, out_i
 
-    def exec(self, xr, xi, yr=None, yi=None):
-        """Forward transform: (C xr + S xi, C xi - S xr) per row."""
-        return self._call(lib().split_dft_exec, xr, xi, yr, yi)
+    def exec(self, xr, xi, yr=None, yi=None, workspace=None):
+        """Forward transform: (C xr + S xi, C xi - S xr) per row.  ``workspace``
+        (optional, two-pass lengths): a contiguous device tensor of at least
+        ``workspace_bytes()`` bytes used instead of the plan's own, so that
+        calls on different streams can overlap."""
+        return self._call(lib().split_dft_exec, lib().split_dft_exec_ws, xr, xi, yr, yi, workspace)
 
-    def adjoint(self, gr, gi, gxr=None, gxi=None):
-        """Adjoint transform: (C gr - S gi, S gr + C gi) per row."""
-        return self._call(lib().split_dft_adjoint, gr, gi, gxr, gxi)
+    def adjoint(self, gr, gi, gxr=None, gxi=None, workspace=None):
+        """Adjoint transform: (C gr - S gi, S gr + C gi) per row (``workspace``
+        as for exec)."""
+        return self._call(lib().split_dft_adjoint, lib().split_dft_adjoint_ws, gr, gi, gxr, gxi, workspace)
 
     def close(self) -> None:
         h, self._h = getattr(self, "_h", None), None

@@ -424,6 +424,37 @@ def test_two_pass_chunks_and_caller_workspace():
                                    yr.data_ptr(), ws, s) == 5
 
 
+def test_two_pass_calls_overlap_on_streams_with_own_workspaces():
+    # one two-pass plan, two side streams, each call with its own workspace
+    # tensor (the Python binding's workspace argument): both results exact
+    n, batch = 1 << 15, 300
+    xs = [inputs.draw_planes(n, batch, "normal", 41 + k) for k in range(2)]
+    refs = [oracle.split_fft_f32(xr.numpy(), xi.numpy()) for xr, xi in xs]
+    adj = oracle.split_adjoint_f32(xs[1][0].numpy(), xs[1][1].numpy())
+    say("  two-pass n=%d batch=%d on two streams" % (n, batch))
+    with Plan(n, batch) as p:
+        ws = p.workspace_bytes()
+        dev = [(xr.cuda(), xi.cuda()) for xr, xi in xs]
+        torch.cuda.synchronize()
+        streams = [torch.cuda.Stream() for _ in range(2)]
+        outs = []
+        for k, st in enumerate(streams):
+            with torch.cuda.stream(st):
+                w = torch.empty(ws // 4, device="cuda")
+                outs.append(p.exec(dev[k][0], dev[k][1], workspace=w))
+        with torch.cuda.stream(streams[1]):
+            w2 = torch.empty(ws // 4, device="cuda")
+            gr, gi = p.adjoint(dev[1][0], dev[1][1], workspace=w2)
+        torch.cuda.synchronize()
+        for (yr, yi), (mr, mi) in zip(outs, refs):
+            assert_bit_exact(to_np(yr), to_np(yi), mr, mi)
+        assert_bit_exact(to_np(gr), to_np(gi), adj[0], adj[1])
+        with pytest.raises(SplitDFTError):
+            p.exec(dev[0][0], dev[0][1], workspace=torch.empty(ws // 4 - 4, device="cuda"))
+        with pytest.raises(ValueError):
+            p.exec(dev[0][0], dev[0][1], workspace=torch.empty(8))
+
+
 def test_single_pass_plans_need_no_workspace():
     with Plan(1024, 8) as p:
         assert p.workspace_bytes() == 0
