@@ -36,8 +36,7 @@ struct split_dft_many_s {
     int variant;  // grouped-kernel build
     int grid;     // persistent workgroups
     std::vector<int64_t> offsets;  // host copy, count + 1 entries
-    int64_t* d_offsets;
-    int32_t* d_order;
+    int64_t* d_offsets;  // offsets of the transforms in length order
     splitdft::ManyItem* d_items_one;   // forward only (direction 0)
     int n_one;
     splitdft::ManyItem* d_items_both;  // forward (0) and adjoint (1) interleaved
@@ -88,8 +87,8 @@ void free_many(split_dft_many_s* p)
     for (ManyLarge& g : p->large)
         if (g.d_rows)
             (void)hipFree(g.d_rows);
-    for (void* q : {static_cast<void*>(p->d_offsets), static_cast<void*>(p->d_order),
-                    static_cast<void*>(p->d_items_one), static_cast<void*>(p->d_items_both),
+    for (void* q : {static_cast<void*>(p->d_offsets), static_cast<void*>(p->d_items_one),
+                    static_cast<void*>(p->d_items_both),
                     static_cast<void*>(p->d_queue), static_cast<void*>(p->d_ws), static_cast<void*>(p->d_tw)})
         if (q)
             (void)hipFree(q);
@@ -210,7 +209,6 @@ split_dft_status many_launch(split_dft_many_t p, const float* xr, const float* x
     if ((d == 2 ? p->n_both : p->n_one) == 0)
         return SPLIT_DFT_OK;
     a.offsets = p->d_offsets;
-    a.order = p->d_order;
     a.items = d == 2 ? p->d_items_both : p->d_items_one;
     a.nitems = d == 2 ? p->n_both : p->n_one;
     a.queue = p->d_queue;
@@ -348,10 +346,12 @@ split_dft_status split_dft_many_plan(split_dft_many_t* out, const int64_t* lengt
     for (size_t j = 0; j < tw.size(); ++j)
         tw[j] = make_float2(c[j], s[j]);
     std::vector<int> queue_init(2, 0);
-    std::vector<int64_t> offs_dev(offs.begin(), offs.end() - 1);
+    // the kernel reads each item's offsets in length order: one load, no
+    // indirection through the sort
+    std::vector<int64_t> offs_dev(order.size());
+    for (size_t i = 0; i < order.size(); ++i)
+        offs_dev[i] = offs[static_cast<size_t>(order[i])];
     e = upload(&p->d_offsets, offs_dev);
-    if (e == hipSuccess)
-        e = upload(&p->d_order, order);
     if (e == hipSuccess)
         e = upload(&p->d_items_one, one);
     if (e == hipSuccess)

@@ -86,11 +86,12 @@ constexpr int kGroupTwM = 13;
 using GroupTw = TwQuarterLds<kGroupTwM>;
 constexpr int kGroupTwEntries = 1 << (kGroupTwM - 2);
 
-// Group item: transforms order[first .. first + count) of length 2^M.
+// Group item: transforms first .. first + count - 1 of the length-sorted list,
+// of length 2^M.
 template <int M>
 __device__ __forceinline__ void many_group_body(Planes pl, const int64_t* __restrict__ offsets,
-                                                const int32_t* __restrict__ order, int64_t first, int count,
-                                                const float2* __restrict__ tw, const float2* s_tw, float* lds,
+                                                int64_t first, int count, const float2* __restrict__ tw,
+                                                const float2* s_tw, float* lds,
                                                 int64_t* s_off, int tid)
 {
     using G = GroupShape<M>;
@@ -100,7 +101,7 @@ __device__ __forceinline__ void many_group_body(Planes pl, const int64_t* __rest
     float* yr = pl.yr;
     float* yi = pl.yi;
     if (tid < count)
-        s_off[tid] = offsets[order[first + tid]];
+        s_off[tid] = offsets[first + tid];
     __syncthreads();
 
     const int slot = tid >> LT;
@@ -184,11 +185,10 @@ __device__ __forceinline__ void many_group_body(Planes pl, const int64_t* __rest
 // into one dispatch, the twelve lengths' code would share, and spill, one).
 template <int M, int WPE>
 __device__ __noinline__ void many_group(Planes pl, const int64_t* __restrict__ offsets,
-                                        const int32_t* __restrict__ order, int64_t first, int count,
-                                        const float2* __restrict__ tw, const float2* s_tw, float* lds,
-                                        int64_t* s_off, int tid)
+                                        int64_t first, int count, const float2* __restrict__ tw,
+                                        const float2* s_tw, float* lds, int64_t* s_off, int tid)
 {
-    many_group_body<M>(pl, offsets, order, first, count, tw, s_tw, lds, s_off, tid);
+    many_group_body<M>(pl, offsets, first, count, tw, s_tw, lds, s_off, tid);
 }
 
 // Large item: one transform through this workgroup's workspace region.
@@ -222,7 +222,7 @@ template <int WPE, bool LARGE>
 __global__ void __launch_bounds__(kMT) __attribute__((amdgpu_waves_per_eu(WPE)))
 split_fft_many_kernel(const float* in_r0, const float* in_i0, float* out_r0, float* out_i0, const float* in_r1,
                       const float* in_i1, float* out_r1, float* out_i1, const int64_t* __restrict__ offsets,
-                      const int32_t* __restrict__ order, const ManyItem* __restrict__ items, int nitems, int* queue,
+                      const ManyItem* __restrict__ items, int nitems, int* queue,
                       float* ws, const float2* __restrict__ tw)
 {
     __shared__ float lds[LARGE ? kLdsWords : kGroupLdsWords];
@@ -252,7 +252,7 @@ split_fft_many_kernel(const float* in_r0, const float* in_i0, float* out_r0, flo
         switch (m) {
 #define SDFT_GROUP(MM)                                                                   \
     case MM:                                                                             \
-        many_group<MM, WPE>(pl, offsets, order, first, count, tw, s_tw, lds, s_off, tid); \
+        many_group<MM, WPE>(pl, offsets, first, count, tw, s_tw, lds, s_off, tid);        \
         break;
             SDFT_GROUP(2)
             SDFT_GROUP(3)
@@ -269,15 +269,15 @@ split_fft_many_kernel(const float* in_r0, const float* in_i0, float* out_r0, flo
 #undef SDFT_GROUP
         case 14:
             if constexpr (LARGE)
-                many_large<P1_14, P2_14, WPE>(pl, offsets[order[first]], ws, tw, lds, tid);
+                many_large<P1_14, P2_14, WPE>(pl, offsets[first], ws, tw, lds, tid);
             break;
         case 15:
             if constexpr (LARGE)
-                many_large<P1_15, P2_15, WPE>(pl, offsets[order[first]], ws, tw, lds, tid);
+                many_large<P1_15, P2_15, WPE>(pl, offsets[first], ws, tw, lds, tid);
             break;
         case 16:
             if constexpr (LARGE)
-                many_large<P1_16, P2_16, WPE>(pl, offsets[order[first]], ws, tw, lds, tid);
+                many_large<P1_16, P2_16, WPE>(pl, offsets[first], ws, tw, lds, tid);
             break;
         default: break;
         }
@@ -304,7 +304,7 @@ hipError_t launch_many(int variant, bool large, const ManyArgs& a, int grid, hip
 {
     auto k = large ? many_kernel<true>(variant) : many_kernel<false>(variant);
     hipLaunchKernelGGL(k, dim3(static_cast<unsigned>(grid)), dim3(kMT), 0, stream, a.in_r[0], a.in_i[0], a.out_r[0],
-                       a.out_i[0], a.in_r[1], a.in_i[1], a.out_r[1], a.out_i[1], a.offsets, a.order, a.items,
+                       a.out_i[0], a.in_r[1], a.in_i[1], a.out_r[1], a.out_i[1], a.offsets, a.items,
                        a.nitems, a.queue, a.ws, a.tw);
     return hipGetLastError();
 }

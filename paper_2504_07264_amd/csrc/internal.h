@@ -72,7 +72,8 @@ constexpr int kManyTwoPassLog2N = 15;
 // memory-side cache)
 constexpr int64_t kManyChunkBytes = int64_t{256} << 20;
 
-// One unit of work: `count` transforms of length 2^m taken from order[first..].
+// One unit of work: `count` transforms of length 2^m, entries [first, first +
+// count) of the length-sorted transform list.
 struct ManyItem {
     int32_t m;
     int32_t dir;    // index into ManyArgs' plane pointers (0 or 1)
@@ -86,8 +87,7 @@ struct ManyArgs {
     const float* in_i[2];
     float* out_r[2];
     float* out_i[2];
-    const int64_t* offsets;  // element offset of transform k in every plane
-    const int32_t* order;    // transform indices, grouped by length
+    const int64_t* offsets;  // element offset in every plane of each transform of the length-sorted list
     const ManyItem* items;
     int nitems;
     int* queue;              // [0] next item, [1] workgroups finished
