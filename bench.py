@@ -162,29 +162,52 @@ def cpu_baseline(xr, xi, gr, gi, budget_s: float = 2.0):
     }
 
 
-def counters_run(reps: int = 5):
-    """Launch the forward length-1024 kernel and a plain device copy of the
-    same byte count (128 MiB read, 128 MiB written) ``reps`` times each, for
+COUNTER_WORKLOADS = ("n1024", "two_pass", "n16384")
+
+
+def counters_run(workload: str = "n1024", reps: int = 5):
+    """Launch the kernels of one workload ``reps`` times, each launch followed
+    by a plain device copy of 128 MiB read and 128 MiB written, for
     hardware-counter collection: the copy's FETCH_SIZE / WRITE_SIZE per
-    dispatch calibrate the counters against known bytes."""
+    dispatch calibrate the counters against known bytes.
+
+    n1024     the forward length-1024 kernel, 16384 rows (the headline)
+    two_pass  forward N=2^15 x 512 and N=2^16 x 256 (both passes each)
+    n16384    forward N=2^14 x 1024 (single pass)
+    """
     import torch
 
     from paper_2504_07264_amd import Plan, inputs
 
     dev = torch.device("cuda", 0)
-    xr, xi = inputs.draw(inputs.HEADLINE_N1024)
-    xr, xi = xr.to(dev), xi.to(dev)
-    yr, yi = torch.empty_like(xr), torch.empty_like(xi)
     src = torch.randn(2, N * BATCH, device=dev)
     dst = torch.empty_like(src)
-    with Plan(N, BATCH) as plan:
-        for _ in range(reps):
-            plan.exec(xr, xi, yr, yi)
-            torch.cuda.synchronize()
-            dst.copy_(src)
-            torch.cuda.synchronize()
-        print(json.dumps({"counters_run": reps, "schedule": plan.describe(),
-                          "copy_bytes_each_way": src.numel() * 4}), flush=True)
+    if workload == "n1024":
+        shapes = [(N, BATCH)]
+    elif workload == "two_pass":
+        shapes = [(1 << 15, 512), (1 << 16, 256)]
+    elif workload == "n16384":
+        shapes = [(1 << 14, 1024)]
+    else:
+        raise SystemExit("unknown counters workload %r (one of %s)" % (workload, ", ".join(COUNTER_WORKLOADS)))
+    report = []
+    for n, batch in shapes:
+        if (n, batch) == (N, BATCH):
+            xr, xi = inputs.draw(inputs.HEADLINE_N1024)
+        else:
+            xr, xi = inputs.draw_planes(n, batch, "normal", 30 + int(math.log2(n)))
+        xr, xi = xr.to(dev), xi.to(dev)
+        yr, yi = torch.empty_like(xr), torch.empty_like(xi)
+        with Plan(n, batch) as plan:
+            for _ in range(reps):
+                plan.exec(xr, xi, yr, yi)
+                torch.cuda.synchronize()
+                dst.copy_(src)
+                torch.cuda.synchronize()
+            report.append({"n": n, "batch": batch, "schedule": plan.describe()})
+        del xr, xi, yr, yi
+    print(json.dumps({"counters_run": reps, "workload": workload, "plans": report,
+                      "copy_bytes_each_way": src.numel() * 4}), flush=True)
 
 
 # executed 16x16x32 matrix-core instructions per length-256 transform (two
@@ -404,8 +427,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mfma", action="store_true", help="skip the matrix-core comparison")
     ap.add_argument("--no-extra", action="store_true", help="skip the N=4096 and ragged side reports")
-    ap.add_argument("--counters", action="store_true",
-                    help="only launch the forward kernel and a calibration copy (for rocprofv3 --pmc)")
+    ap.add_argument("--counters", nargs="?", const="n1024", default=None, choices=COUNTER_WORKLOADS,
+                    help="only launch one workload's kernels and a calibration copy (for rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the benchmark runs on one GPU only; the transforms are independent per row, "
@@ -414,7 +437,7 @@ def main():
         sys.exit(2)
 
     if args.counters:
-        counters_run()
+        counters_run(args.counters)
         return
 
     import torch

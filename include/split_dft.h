@@ -23,9 +23,15 @@
  * Layout: each plane is a contiguous row-major [batch][N] array of float.
  *
  * Ownership: all data pointers are device memory owned by the caller.  A plan
- * owns its device tables (twiddles; matrix-core constants) and, for two-pass
- * lengths, a workspace: allocated by split_dft_plan, freed by
- * split_dft_destroy.
+ * owns its device tables (twiddles; matrix-core constants), allocated by
+ * split_dft_plan and freed by split_dft_destroy.  Two-pass lengths (and
+ * grouped plans that contain them) also need a workspace of
+ * split_dft_workspace_bytes(plan) bytes: by default the plan allocates and
+ * owns one; a plan created with SPLIT_DFT_CALLER_WORKSPACE allocates none,
+ * and every call then takes the caller's (the *_ws entry points; the Python
+ * binding allocates it through torch's caching allocator on the calling
+ * stream), so that large allocations go through the caller's allocator and
+ * calls on several streams never share one.
  *
  * Errors: every entry point returns a status and never aborts or throws.
  * Arguments are validated before any HIP call; on a validation failure no
@@ -96,8 +102,13 @@ typedef enum {
  * eq. (9), y_2N = S D^(1) W^(1) ... D^(m) W^(m) x_2N (stages m down to 1,
  * butterfly before rotation, the bit reversal last), FP32, n <= 2^14; results
  * are bit-identical to those factors applied in that order with the
- * operation forms above.  Other bits must be 0. */
+ * operation forms above. */
 #define SPLIT_DFT_DIF (1u << 24)
+/* Bit 30 (batched and grouped plans): allocate no workspace; calls on a plan
+ * whose workspace_bytes is nonzero must then pass one (a NULL workspace
+ * fails with SPLIT_DFT_ERR_NULL_POINTER). */
+#define SPLIT_DFT_CALLER_WORKSPACE (1u << 30)
+/* (Batched plans: bits 16-23, 25-29 and 31 must be 0.) */
 
 /* Largest supported log2 N. */
 #define SPLIT_DFT_MAX_LOG2N 16
@@ -145,6 +156,26 @@ split_dft_status split_dft_exec_ws(split_dft_plan_t plan, const float *xr, const
 split_dft_status split_dft_adjoint_ws(split_dft_plan_t plan, const float *gr, const float *gi,
                                       float *gxr, float *gxi, void *workspace,
                                       size_t workspace_bytes, void *stream);
+
+/*
+ * Forward transform of (xr, xi) into (yr, yi) and adjoint transform of
+ * (gr, gi) into (gxr, gxi) in one call: eq. (5) and its transpose E_2N^T,
+ * the two halves of a differentiable step when both inputs are at hand.
+ * Single-pass FP32 schedules run both directions in one kernel launch (the
+ * grid covers the forward rows, then the adjoint rows); two-pass and
+ * matrix-core plans run them one after the other on the stream.  Each
+ * direction follows the rules of split_dft_exec; in addition no array of one
+ * direction may overlap an array of the other (SPLIT_DFT_ERR_ALIASING).
+ * Results are bit-identical to split_dft_exec and split_dft_adjoint.
+ */
+split_dft_status split_dft_exec_adjoint(split_dft_plan_t plan, const float *xr, const float *xi, float *yr,
+                                        float *yi, const float *gr, const float *gi, float *gxr, float *gxi,
+                                        void *stream);
+/* As split_dft_exec_adjoint, with a caller-owned workspace (rules of
+ * split_dft_exec_ws; both directions use it one after the other). */
+split_dft_status split_dft_exec_adjoint_ws(split_dft_plan_t plan, const float *xr, const float *xi, float *yr,
+                                           float *yi, const float *gr, const float *gi, float *gxr, float *gxi,
+                                           void *workspace, size_t workspace_bytes, void *stream);
 
 /* Release a plan and its device table.  NULL is accepted and ignored. */
 split_dft_status split_dft_destroy(split_dft_plan_t plan);
@@ -202,10 +233,11 @@ typedef struct split_dft_graph_s *split_dft_graph_t;
  * workgroups per CU (0 = as many as fit); SPLIT_DFT_MANY_ONE_KERNEL; bits
  * 25-29: t, the lengths from 2^t up run in per-length launches (0 = the
  * default 12; 10 <= t <= 17, 17 = none).
- * Allocates the device-side item list, offsets and twiddle table, and a
- * workspace: with SPLIT_DFT_MANY_ONE_KERNEL and some length >= 2^14, 512 KiB
- * per persistent workgroup; by default, when some length is 2^15 or more, one
- * two-pass chunk (at most 256 MiB). */
+ * Allocates the device-side item list, offsets and twiddle table, and
+ * (unless SPLIT_DFT_CALLER_WORKSPACE is set) a workspace: with
+ * SPLIT_DFT_MANY_ONE_KERNEL and some length >= 2^14, 512 KiB per persistent
+ * workgroup; by default, when some length is 2^15 or more, one two-pass chunk
+ * (at most 256 MiB). */
 #define SPLIT_DFT_MANY_ONE_KERNEL (1u << 24)
 split_dft_status split_dft_many_plan(split_dft_many_t *out, const int64_t *lengths, int64_t count,
                                      uint32_t flags);
@@ -214,6 +246,10 @@ split_dft_status split_dft_many_offsets(split_dft_many_t plan, int64_t *offsets)
 /* Any pointer may be NULL. */
 split_dft_status split_dft_many_info(split_dft_many_t plan, int64_t *count, int64_t *points,
                                      int *workgroups, int *items, size_t *workspace_bytes);
+/* Workspace bytes the grouped plan's calls need (0 if none; the plan's own
+ * unless it was created with SPLIT_DFT_CALLER_WORKSPACE); 0 for a NULL or
+ * destroyed plan. */
+size_t split_dft_many_workspace_bytes(split_dft_many_t plan);
 /* Forward transforms of every (xr, xi) row into (yr, yi). */
 split_dft_status split_dft_many_exec(split_dft_many_t plan, const float *xr, const float *xi,
                                      float *yr, float *yi, void *stream);
@@ -225,12 +261,34 @@ split_dft_status split_dft_many_adjoint(split_dft_many_t plan, const float *gr, 
 split_dft_status split_dft_many_exec_adjoint(split_dft_many_t plan, const float *xr, const float *xi,
                                              float *yr, float *yi, const float *gr, const float *gi,
                                              float *gxr, float *gxi, void *stream);
+/* The three calls above with a caller-owned workspace of at least
+ * split_dft_many_workspace_bytes(plan) bytes (device memory, 16-byte
+ * aligned, overlapping no data array); NULL = the plan's own (an error for a
+ * SPLIT_DFT_CALLER_WORKSPACE plan that needs one).  Everything is validated
+ * before the first HIP call. */
+split_dft_status split_dft_many_exec_ws(split_dft_many_t plan, const float *xr, const float *xi, float *yr,
+                                        float *yi, void *workspace, size_t workspace_bytes, void *stream);
+split_dft_status split_dft_many_adjoint_ws(split_dft_many_t plan, const float *gr, const float *gi, float *gxr,
+                                           float *gxi, void *workspace, size_t workspace_bytes, void *stream);
+split_dft_status split_dft_many_exec_adjoint_ws(split_dft_many_t plan, const float *xr, const float *xi,
+                                                float *yr, float *yi, const float *gr, const float *gi,
+                                                float *gxr, float *gxi, void *workspace,
+                                                size_t workspace_bytes, void *stream);
 /* Capture split_dft_many_exec_adjoint (or split_dft_many_exec when gr, gi,
  * gxr, gxi are all NULL) on these fixed buffers into an instantiated HIP
- * graph, using a private capturing stream. */
+ * graph, using a private capturing stream.  The graph refers to the data
+ * arrays (and the caller's workspace, _ws form) by address: the caller keeps
+ * them allocated while the graph exists.  It also uses the plan's device
+ * data, which the library keeps allocated until the plan AND every graph
+ * captured from it are destroyed, in any order: after split_dft_many_destroy
+ * the plan handle is invalid for every other call, but its graphs still
+ * launch correctly. */
 split_dft_status split_dft_many_graph(split_dft_many_t plan, const float *xr, const float *xi,
                                       float *yr, float *yi, const float *gr, const float *gi,
                                       float *gxr, float *gxi, split_dft_graph_t *out);
+split_dft_status split_dft_many_graph_ws(split_dft_many_t plan, const float *xr, const float *xi, float *yr,
+                                         float *yi, const float *gr, const float *gi, float *gxr, float *gxi,
+                                         void *workspace, size_t workspace_bytes, split_dft_graph_t *out);
 split_dft_status split_dft_graph_launch(split_dft_graph_t graph, void *stream);
 split_dft_status split_dft_graph_destroy(split_dft_graph_t graph);
 split_dft_status split_dft_many_destroy(split_dft_many_t plan);

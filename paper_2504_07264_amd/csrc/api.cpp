@@ -126,14 +126,57 @@ split_dft_status validate_io(const split_dft_plan_s* p, const float* xr, const f
     return SPLIT_DFT_OK;
 }
 
-split_dft_status run(split_dft_plan_t p, const float* xr, const float* xi, float* yr, float* yi, void* ws,
-                     size_t ws_bytes, void* stream)
+// Planes of one direction of a call.
+struct Io {
+    const float* xr;
+    const float* xi;
+    float* yr;
+    float* yi;
+};
+
+// One or two directions (dir[1].xr == NULL: one) on the caller's stream.  A
+// second direction runs in the same launch as the first where the schedule
+// allows (single-pass FP32), else after it; its arrays may not overlap the
+// first direction's.
+split_dft_status run(split_dft_plan_t p, const Io* dir, int ndir, void* ws, size_t ws_bytes, void* stream)
 {
     if (!p || !plan_is_live(p))
         return fail(SPLIT_DFT_ERR_INVALID_PLAN, "plan is NULL, destroyed or not created by split_dft_plan");
-    const split_dft_status vs = validate_io(p, xr, xi, yr, yi);
-    if (vs != SPLIT_DFT_OK)
-        return vs;
+    for (int k = 0; k < ndir; ++k) {
+        const split_dft_status vs = validate_io(p, dir[k].xr, dir[k].xi, dir[k].yr, dir[k].yi);
+        if (vs != SPLIT_DFT_OK)
+            return vs;
+    }
+    const size_t bytes = static_cast<size_t>(p->n) * static_cast<size_t>(p->batch) * sizeof(float);
+    if (ndir == 2) {
+        // the directions may run concurrently: no output of one may touch the other's arrays
+        for (int k = 0; k < 2; ++k)
+            for (const float* out : {dir[k].yr, dir[k].yi})
+                for (const float* other : {dir[1 - k].xr, dir[1 - k].xi, static_cast<const float*>(dir[1 - k].yr),
+                                           static_cast<const float*>(dir[1 - k].yi)})
+                    if (ranges_overlap(out, bytes, other, bytes))
+                        return fail(SPLIT_DFT_ERR_ALIASING, "forward and adjoint arrays overlap");
+    }
+    float* w = static_cast<float*>(ws);
+    if (p->two) {
+        if (!w) {
+            w = p->d_ws;
+            if (!w)
+                return fail(SPLIT_DFT_ERR_NULL_POINTER,
+                            "the plan was created with SPLIT_DFT_CALLER_WORKSPACE: pass a workspace of "
+                            "split_dft_workspace_bytes(plan) = " + std::to_string(p->ws_bytes) + " bytes");
+        } else {
+            if (ws_bytes < p->ws_bytes)
+                return fail(SPLIT_DFT_ERR_INVALID_BATCH, "workspace smaller than split_dft_workspace_bytes");
+            if (reinterpret_cast<uintptr_t>(w) % 16 != 0)
+                return fail(SPLIT_DFT_ERR_MISALIGNED, "workspace must be 16-byte aligned");
+            for (int k = 0; k < ndir; ++k)
+                for (const void* q : {static_cast<const void*>(dir[k].xr), static_cast<const void*>(dir[k].xi),
+                                      static_cast<const void*>(dir[k].yr), static_cast<const void*>(dir[k].yi)})
+                    if (ranges_overlap(w, p->ws_bytes, q, bytes))
+                        return fail(SPLIT_DFT_ERR_ALIASING, "workspace overlaps a data array");
+        }
+    }
     // the plan's tables live on the device it was created on
     int cur = -1;
     if (hipGetDevice(&cur) != hipSuccess || cur != p->device)
@@ -141,43 +184,43 @@ split_dft_status run(split_dft_plan_t p, const float* xr, const float* xi, float
                                                     ", the current device is " + std::to_string(cur));
     const hipStream_t st = static_cast<hipStream_t>(stream);
     if (p->two) {
-        float* w = static_cast<float*>(ws);
-        if (!w) {
-            w = p->d_ws;
-        } else {
-            if (ws_bytes < p->ws_bytes)
-                return fail(SPLIT_DFT_ERR_INVALID_BATCH, "workspace smaller than split_dft_workspace_bytes");
-            if (reinterpret_cast<uintptr_t>(w) % 16 != 0)
-                return fail(SPLIT_DFT_ERR_MISALIGNED, "workspace must be 16-byte aligned");
-            const size_t bytes = static_cast<size_t>(p->n) * static_cast<size_t>(p->batch) * sizeof(float);
-            for (const void* q : {static_cast<const void*>(xr), static_cast<const void*>(xi),
-                                  static_cast<const void*>(yr), static_cast<const void*>(yi)})
-                if (ranges_overlap(w, p->ws_bytes, q, bytes))
-                    return fail(SPLIT_DFT_ERR_ALIASING, "workspace overlaps a data array");
-        }
         float* wr = w;
         float* wi = w + p->chunk * p->n;
-        for (int64_t s0 = 0; s0 < p->batch; s0 += p->chunk) {
-            const int64_t k = p->batch - s0 < p->chunk ? p->batch - s0 : p->chunk;
-            const int64_t off = s0 * p->n;
-            hipError_t e = p->two->pass1(xr + off, xi + off, wr, wi, p->d_tw, k, nullptr, st);
-            if (e == hipSuccess)
-                e = p->two->pass2(wr, wi, yr + off, yi + off, p->d_tw, k, nullptr, st);
-            if (e != hipSuccess)
-                return fail_hip(e, "two-pass kernel launch");
-        }
+        for (int k = 0; k < ndir; ++k)
+            for (int64_t s0 = 0; s0 < p->batch; s0 += p->chunk) {
+                const int64_t c = p->batch - s0 < p->chunk ? p->batch - s0 : p->chunk;
+                const int64_t off = s0 * p->n;
+                hipError_t e = p->two->pass1(dir[k].xr + off, dir[k].xi + off, wr, wi, p->d_tw, c, nullptr, st);
+                if (e == hipSuccess)
+                    e = p->two->pass2(wr, wi, dir[k].yr + off, dir[k].yi + off, p->d_tw, c, nullptr, st);
+                if (e != hipSuccess)
+                    return fail_hip(e, "two-pass kernel launch");
+            }
         return SPLIT_DFT_OK;
     }
-    const hipError_t e =
-        p->mode == splitdft::kModeFP32
-            ? p->variant->launch(xr, xi, yr, yi, p->d_tw, p->batch, nullptr, st)
-            : splitdft::launch_mfma(p->mode, p->m, xr, xi, yr, yi, p->d_mfma,
-                                    reinterpret_cast<const float2*>(p->d_mfma + splitdft::kMfmaConstFloats),
-                                    p->batch, st);
-    if (e != hipSuccess)
-        return fail_hip(e, "kernel launch");
+    if (p->mode == splitdft::kModeFP32) {
+        const splitdft::Dir2 second{dir[1].xr, dir[1].xi, dir[1].yr, dir[1].yi};
+        const hipError_t e = p->variant->launch(dir[0].xr, dir[0].xi, dir[0].yr, dir[0].yi, p->d_tw, p->batch,
+                                                nullptr, st, ndir == 2 ? &second : nullptr);
+        if (e != hipSuccess)
+            return fail_hip(e, "kernel launch");
+        return SPLIT_DFT_OK;
+    }
+    for (int k = 0; k < ndir; ++k) {
+        const hipError_t e =
+            splitdft::launch_mfma(p->mode, p->m, dir[k].xr, dir[k].xi, dir[k].yr, dir[k].yi, p->d_mfma,
+                                  reinterpret_cast<const float2*>(p->d_mfma + splitdft::kMfmaConstFloats), p->batch,
+                                  st);
+        if (e != hipSuccess)
+            return fail_hip(e, "kernel launch");
+    }
     return SPLIT_DFT_OK;
 }
+
+// C gr - S gi = imaginary part and S gr + C gi = real part of the forward
+// transform of (gi, gr): the adjoint is the forward kernel with both plane
+// pairs exchanged.
+Io adjoint_io(const float* gr, const float* gi, float* gxr, float* gxi) { return Io{gi, gr, gxi, gxr}; }
 
 }  // namespace
 
@@ -197,7 +240,8 @@ split_dft_status split_dft_plan(split_dft_plan_t* out, int64_t n, int64_t batch,
     const uint32_t precision = flags & 0xffu;
     const uint32_t vsel = (flags >> 8) & 0xffu;  // 0 = default schedule, k = compiled schedule k-1
     const bool dif = (flags & SPLIT_DFT_DIF) != 0;
-    if (precision > SPLIT_DFT_BF16X3 || ((flags & ~SPLIT_DFT_DIF) >> 16) != 0)
+    const bool caller_ws = (flags & SPLIT_DFT_CALLER_WORKSPACE) != 0;
+    if (precision > SPLIT_DFT_BF16X3 || ((flags & ~(SPLIT_DFT_DIF | SPLIT_DFT_CALLER_WORKSPACE)) >> 16) != 0)
         return fail(SPLIT_DFT_ERR_UNSUPPORTED, "unsupported flags " + std::to_string(flags));
     const int mode = static_cast<int>(precision);
     if (mode != splitdft::kModeFP32 && (m != 8 || vsel != 0 || dif))
@@ -284,7 +328,7 @@ split_dft_status split_dft_plan(split_dft_plan_t* out, int64_t n, int64_t batch,
         const int64_t nchunks = (batch + chunk - 1) / chunk;
         chunk = (batch + nchunks - 1) / nchunks;
         ws_bytes = static_cast<size_t>(chunk) * static_cast<size_t>(n) * 2 * sizeof(float);
-        e = hipMalloc(&d_ws, ws_bytes);
+        e = caller_ws ? hipSuccess : hipMalloc(&d_ws, ws_bytes);
         if (e != hipSuccess) {
             if (d_mfma)
                 (void)hipFree(d_mfma);
@@ -320,28 +364,45 @@ split_dft_status split_dft_plan(split_dft_plan_t* out, int64_t n, int64_t batch,
 split_dft_status split_dft_exec(split_dft_plan_t plan, const float* xr, const float* xi, float* yr, float* yi,
                                 void* stream)
 {
-    return run(plan, xr, xi, yr, yi, nullptr, 0, stream);
+    const Io io[2] = {{xr, xi, yr, yi}, {}};
+    return run(plan, io, 1, nullptr, 0, stream);
 }
 
 split_dft_status split_dft_exec_ws(split_dft_plan_t plan, const float* xr, const float* xi, float* yr, float* yi,
                                    void* workspace, size_t workspace_bytes, void* stream)
 {
-    return run(plan, xr, xi, yr, yi, workspace, workspace_bytes, stream);
-}
-
-split_dft_status split_dft_adjoint_ws(split_dft_plan_t plan, const float* gr, const float* gi, float* gxr,
-                                      float* gxi, void* workspace, size_t workspace_bytes, void* stream)
-{
-    return run(plan, gi, gr, gxi, gxr, workspace, workspace_bytes, stream);
+    const Io io[2] = {{xr, xi, yr, yi}, {}};
+    return run(plan, io, 1, workspace, workspace_bytes, stream);
 }
 
 split_dft_status split_dft_adjoint(split_dft_plan_t plan, const float* gr, const float* gi, float* gxr, float* gxi,
                                    void* stream)
 {
-    // C gr - S gi = imaginary part and S gr + C gi = real part of the forward
-    // transform of (gi, gr): the adjoint is the forward kernel with both
-    // plane pairs exchanged.
-    return run(plan, gi, gr, gxi, gxr, nullptr, 0, stream);
+    const Io io[2] = {adjoint_io(gr, gi, gxr, gxi), {}};
+    return run(plan, io, 1, nullptr, 0, stream);
+}
+
+split_dft_status split_dft_adjoint_ws(split_dft_plan_t plan, const float* gr, const float* gi, float* gxr,
+                                      float* gxi, void* workspace, size_t workspace_bytes, void* stream)
+{
+    const Io io[2] = {adjoint_io(gr, gi, gxr, gxi), {}};
+    return run(plan, io, 1, workspace, workspace_bytes, stream);
+}
+
+split_dft_status split_dft_exec_adjoint(split_dft_plan_t plan, const float* xr, const float* xi, float* yr,
+                                        float* yi, const float* gr, const float* gi, float* gxr, float* gxi,
+                                        void* stream)
+{
+    const Io io[2] = {{xr, xi, yr, yi}, adjoint_io(gr, gi, gxr, gxi)};
+    return run(plan, io, 2, nullptr, 0, stream);
+}
+
+split_dft_status split_dft_exec_adjoint_ws(split_dft_plan_t plan, const float* xr, const float* xi, float* yr,
+                                           float* yi, const float* gr, const float* gi, float* gxr, float* gxi,
+                                           void* workspace, size_t workspace_bytes, void* stream)
+{
+    const Io io[2] = {{xr, xi, yr, yi}, adjoint_io(gr, gi, gxr, gxi)};
+    return run(plan, io, 2, workspace, workspace_bytes, stream);
 }
 
 split_dft_status split_dft_destroy(split_dft_plan_t plan)

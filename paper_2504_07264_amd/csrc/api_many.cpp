@@ -42,14 +42,19 @@ struct split_dft_many_s {
     splitdft::ManyItem* d_items_both;  // forward (0) and adjoint (1) interleaved
     int n_both;
     int* d_queue;
-    float* d_ws;
-    size_t ws_bytes;
+    float* d_ws;     // plan-owned workspace (NULL with SPLIT_DFT_CALLER_WORKSPACE)
+    size_t ws_bytes; // workspace the plan's launches need
     float2* d_tw;
+    // device data stays allocated while the handle is live or any captured
+    // graph refers to it: destroy drops the handle's reference, each graph
+    // holds one (guarded by g_mu)
+    int refs;
 };
 
 struct split_dft_graph_s {
     hipGraph_t graph;
     hipGraphExec_t exec;
+    split_dft_many_s* plan;  // whose device data the graph's kernels use
 };
 
 namespace {
@@ -76,12 +81,20 @@ void set_live(const void* p, bool on)
         live().erase(p);
 }
 
+// Remove p from the live set; false if it was not there.
+bool take_live(const void* p)
+{
+    std::lock_guard<std::mutex> g(g_mu);
+    return live().erase(p) != 0;
+}
+
 bool ranges_overlap(const void* a, size_t abytes, const void* b, size_t bbytes)
 {
     const auto x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
     return x < y + bbytes && y < x + abytes;
 }
 
+// Free a grouped plan's device data and host record (its device current).
 void free_many(split_dft_many_s* p)
 {
     for (ManyLarge& g : p->large)
@@ -93,6 +106,24 @@ void free_many(split_dft_many_s* p)
         if (q)
             (void)hipFree(q);
     delete p;
+}
+
+// Drop one reference to a plan's device data; the last one frees it (on the
+// plan's device).
+void release_many(split_dft_many_s* p)
+{
+    {
+        std::lock_guard<std::mutex> g(g_mu);
+        if (--p->refs > 0)
+            return;
+    }
+    int cur = 0;
+    const bool sw = hipGetDevice(&cur) == hipSuccess && cur != p->device;
+    if (sw)
+        (void)hipSetDevice(p->device);
+    free_many(p);
+    if (sw)
+        (void)hipSetDevice(cur);
 }
 
 template <class T>
@@ -137,18 +168,14 @@ split_dft_status check_dir(const split_dft_many_s* p, const float* ar, const flo
     return SPLIT_DFT_OK;
 }
 
-split_dft_status many_launch(split_dft_many_t p, const float* xr, const float* xi, float* yr, float* yi,
-                             const float* gr, const float* gi, float* gxr, float* gxi, bool fwd, bool adj,
-                             hipStream_t stream, std::string* msg)
+// Validate a grouped call (plan, planes of each direction, cross-direction
+// overlap, workspace); makes no HIP call.
+split_dft_status many_validate(split_dft_many_t p, const float* xr, const float* xi, float* yr, float* yi,
+                               const float* gr, const float* gi, float* gxr, float* gxi, bool fwd, bool adj,
+                               const void* ws, size_t ws_bytes, std::string* msg)
 {
     if (!p || !is_live(p)) {
         *msg = "grouped plan is NULL, destroyed or not created by split_dft_many_plan";
-        return SPLIT_DFT_ERR_INVALID_PLAN;
-    }
-    int cur = -1;  // the plan's tables and workspace live on the device it was created on
-    if (hipGetDevice(&cur) != hipSuccess || cur != p->device) {
-        *msg = "the grouped plan belongs to HIP device " + std::to_string(p->device) + ", the current device is " +
-               std::to_string(cur);
         return SPLIT_DFT_ERR_INVALID_PLAN;
     }
     const size_t bytes = static_cast<size_t>(p->points) * sizeof(float);
@@ -172,6 +199,50 @@ split_dft_status many_launch(split_dft_many_t p, const float* xr, const float* x
                     return SPLIT_DFT_ERR_ALIASING;
                 }
     }
+    if (p->ws_bytes > 0) {
+        if (!ws && !p->d_ws) {
+            *msg = "the grouped plan was created with SPLIT_DFT_CALLER_WORKSPACE: pass a workspace of "
+                   "split_dft_many_workspace_bytes(plan) = " + std::to_string(p->ws_bytes) + " bytes";
+            return SPLIT_DFT_ERR_NULL_POINTER;
+        }
+        if (ws) {
+            if (ws_bytes < p->ws_bytes) {
+                *msg = "workspace smaller than split_dft_many_workspace_bytes";
+                return SPLIT_DFT_ERR_INVALID_BATCH;
+            }
+            if (reinterpret_cast<uintptr_t>(ws) % 16 != 0) {
+                *msg = "workspace must be 16-byte aligned";
+                return SPLIT_DFT_ERR_MISALIGNED;
+            }
+            for (const void* q : {static_cast<const void*>(xr), static_cast<const void*>(xi),
+                                  static_cast<const void*>(yr), static_cast<const void*>(yi),
+                                  static_cast<const void*>(gr), static_cast<const void*>(gi),
+                                  static_cast<const void*>(gxr), static_cast<const void*>(gxi)})
+                if (q && ranges_overlap(ws, p->ws_bytes, q, bytes)) {
+                    *msg = "workspace overlaps a data array";
+                    return SPLIT_DFT_ERR_ALIASING;
+                }
+        }
+    }
+    return SPLIT_DFT_OK;
+}
+
+// Validate, then launch on `stream`.  ws: the caller's workspace, or NULL for
+// the plan's own.
+split_dft_status many_launch(split_dft_many_t p, const float* xr, const float* xi, float* yr, float* yi,
+                             const float* gr, const float* gi, float* gxr, float* gxi, bool fwd, bool adj,
+                             void* ws, size_t ws_bytes, hipStream_t stream, std::string* msg)
+{
+    split_dft_status st = many_validate(p, xr, xi, yr, yi, gr, gi, gxr, gxi, fwd, adj, ws, ws_bytes, msg);
+    if (st != SPLIT_DFT_OK)
+        return st;
+    int cur = -1;  // the plan's tables and workspace live on the device it was created on
+    if (hipGetDevice(&cur) != hipSuccess || cur != p->device) {
+        *msg = "the grouped plan belongs to HIP device " + std::to_string(p->device) + ", the current device is " +
+               std::to_string(cur);
+        return SPLIT_DFT_ERR_INVALID_PLAN;
+    }
+    float* work = ws ? static_cast<float*>(ws) : p->d_ws;
     splitdft::ManyArgs a{};
     int d = 0;
     if (fwd) {
@@ -189,10 +260,10 @@ split_dft_status many_launch(split_dft_many_t p, const float* xr, const float* x
             hipError_t e = hipSuccess;
             if (g.variant) {
                 e = g.variant->launch(a.in_r[k], a.in_i[k], a.out_r[k], a.out_i[k], p->d_tw, g.count, g.d_rows,
-                                      stream);
+                                      stream, nullptr);
             } else {
-                float* wr = p->d_ws;
-                float* wi = p->d_ws + g.chunk * (int64_t{1} << g.m);
+                float* wr = work;
+                float* wi = work + g.chunk * (int64_t{1} << g.m);
                 for (int64_t s0 = 0; s0 < g.count && e == hipSuccess; s0 += g.chunk) {
                     const int64_t c = g.count - s0 < g.chunk ? g.count - s0 : g.chunk;
                     e = g.two->pass1(a.in_r[k], a.in_i[k], wr, wi, p->d_tw, c, g.d_rows + s0, stream);
@@ -212,7 +283,7 @@ split_dft_status many_launch(split_dft_many_t p, const float* xr, const float* x
     a.items = d == 2 ? p->d_items_both : p->d_items_one;
     a.nitems = d == 2 ? p->n_both : p->n_one;
     a.queue = p->d_queue;
-    a.ws = p->d_ws;
+    a.ws = work;
     a.tw = p->d_tw;
     const hipError_t e = splitdft::launch_many(p->variant, p->large_items, a, p->grid, stream);
     if (e != hipSuccess) {
@@ -239,7 +310,8 @@ split_dft_status split_dft_many_plan(split_dft_many_t* out, const int64_t* lengt
         return fail(SPLIT_DFT_ERR_NULL_POINTER, "out or lengths is NULL");
     if (count < 1 || count > INT32_MAX)
         return fail(SPLIT_DFT_ERR_INVALID_BATCH, "count must be in [1, 2^31 - 1]");
-    if ((flags & 0xffu) != SPLIT_DFT_FP32 || (flags >> 30) != 0)
+    const bool caller_ws = (flags & SPLIT_DFT_CALLER_WORKSPACE) != 0;
+    if ((flags & 0xffu) != SPLIT_DFT_FP32 || ((flags & ~SPLIT_DFT_CALLER_WORKSPACE) >> 30) != 0)
         return fail(SPLIT_DFT_ERR_UNSUPPORTED, "unsupported flags " + std::to_string(flags));
     const bool one_kernel = (flags & SPLIT_DFT_MANY_ONE_KERNEL) != 0;
     // bits 25-29: log2 of the shortest length run by per-length launches
@@ -404,7 +476,8 @@ split_dft_status split_dft_many_plan(split_dft_many_t* out, const int64_t* lengt
     }
     if (e == hipSuccess && std::max(ws1, ws2) > 0) {
         p->ws_bytes = std::max(ws1, ws2);
-        e = hipMalloc(&p->d_ws, p->ws_bytes);
+        if (!caller_ws)
+            e = hipMalloc(&p->d_ws, p->ws_bytes);
     }
     if (e != hipSuccess) {
         free_many(p);
@@ -413,6 +486,7 @@ split_dft_status split_dft_many_plan(split_dft_many_t* out, const int64_t* lengt
     }
     p->n_one = static_cast<int>(one.size());
     p->n_both = static_cast<int>(both.size());
+    p->refs = 1;
     set_live(p, true);
     *out = p;
     return SPLIT_DFT_OK;
@@ -446,21 +520,40 @@ split_dft_status split_dft_many_info(split_dft_many_t plan, int64_t* count, int6
     return SPLIT_DFT_OK;
 }
 
+size_t split_dft_many_workspace_bytes(split_dft_many_t plan)
+{
+    if (!plan || !is_live(plan))
+        return 0;
+    return plan->ws_bytes;
+}
+
 split_dft_status split_dft_many_exec(split_dft_many_t plan, const float* xr, const float* xi, float* yr, float* yi,
                                      void* stream)
 {
+    return split_dft_many_exec_ws(plan, xr, xi, yr, yi, nullptr, 0, stream);
+}
+
+split_dft_status split_dft_many_exec_ws(split_dft_many_t plan, const float* xr, const float* xi, float* yr,
+                                        float* yi, void* workspace, size_t workspace_bytes, void* stream)
+{
     std::string msg;
     const split_dft_status st = many_launch(plan, xr, xi, yr, yi, nullptr, nullptr, nullptr, nullptr, true, false,
-                                            static_cast<hipStream_t>(stream), &msg);
+                                            workspace, workspace_bytes, static_cast<hipStream_t>(stream), &msg);
     return st == SPLIT_DFT_OK ? st : fail(st, msg);
 }
 
 split_dft_status split_dft_many_adjoint(split_dft_many_t plan, const float* gr, const float* gi, float* gxr,
                                         float* gxi, void* stream)
 {
+    return split_dft_many_adjoint_ws(plan, gr, gi, gxr, gxi, nullptr, 0, stream);
+}
+
+split_dft_status split_dft_many_adjoint_ws(split_dft_many_t plan, const float* gr, const float* gi, float* gxr,
+                                           float* gxi, void* workspace, size_t workspace_bytes, void* stream)
+{
     std::string msg;
     const split_dft_status st = many_launch(plan, nullptr, nullptr, nullptr, nullptr, gr, gi, gxr, gxi, false, true,
-                                            static_cast<hipStream_t>(stream), &msg);
+                                            workspace, workspace_bytes, static_cast<hipStream_t>(stream), &msg);
     return st == SPLIT_DFT_OK ? st : fail(st, msg);
 }
 
@@ -468,9 +561,16 @@ split_dft_status split_dft_many_exec_adjoint(split_dft_many_t plan, const float*
                                              float* yi, const float* gr, const float* gi, float* gxr, float* gxi,
                                              void* stream)
 {
+    return split_dft_many_exec_adjoint_ws(plan, xr, xi, yr, yi, gr, gi, gxr, gxi, nullptr, 0, stream);
+}
+
+split_dft_status split_dft_many_exec_adjoint_ws(split_dft_many_t plan, const float* xr, const float* xi, float* yr,
+                                                float* yi, const float* gr, const float* gi, float* gxr, float* gxi,
+                                                void* workspace, size_t workspace_bytes, void* stream)
+{
     std::string msg;
-    const split_dft_status st =
-        many_launch(plan, xr, xi, yr, yi, gr, gi, gxr, gxi, true, true, static_cast<hipStream_t>(stream), &msg);
+    const split_dft_status st = many_launch(plan, xr, xi, yr, yi, gr, gi, gxr, gxi, true, true, workspace,
+                                            workspace_bytes, static_cast<hipStream_t>(stream), &msg);
     return st == SPLIT_DFT_OK ? st : fail(st, msg);
 }
 
@@ -478,30 +578,39 @@ split_dft_status split_dft_many_graph(split_dft_many_t plan, const float* xr, co
                                       const float* gr, const float* gi, float* gxr, float* gxi,
                                       split_dft_graph_t* out)
 {
+    return split_dft_many_graph_ws(plan, xr, xi, yr, yi, gr, gi, gxr, gxi, nullptr, 0, out);
+}
+
+split_dft_status split_dft_many_graph_ws(split_dft_many_t plan, const float* xr, const float* xi, float* yr,
+                                         float* yi, const float* gr, const float* gi, float* gxr, float* gxi,
+                                         void* workspace, size_t workspace_bytes, split_dft_graph_t* out)
+{
     if (!out)
         return fail(SPLIT_DFT_ERR_NULL_POINTER, "out is NULL");
     const bool adj = gr || gi || gxr || gxi;
     // validate before touching the runtime
     {
         std::string msg;
-        if (!plan || !is_live(plan))
-            return fail(SPLIT_DFT_ERR_INVALID_PLAN, "grouped plan is NULL or destroyed");
-        split_dft_status st = check_dir(plan, xr, xi, yr, yi, &msg);
-        if (st == SPLIT_DFT_OK && adj)
-            st = check_dir(plan, gr, gi, gxr, gxi, &msg);
+        const split_dft_status st = many_validate(plan, xr, xi, yr, yi, gr, gi, gxr, gxi, true, adj, workspace,
+                                                  workspace_bytes, &msg);
         if (st != SPLIT_DFT_OK)
             return fail(st, msg);
     }
+    auto* g = new (std::nothrow) split_dft_graph_s{nullptr, nullptr, plan};
+    if (!g)
+        return fail(SPLIT_DFT_ERR_OUT_OF_MEMORY, "host allocation of the graph");
     hipStream_t s = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
-    if (e != hipSuccess)
+    if (e != hipSuccess) {
+        delete g;
         return fail(SPLIT_DFT_ERR_HIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+    }
     hipGraph_t graph = nullptr;
     e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     std::string msg;
     split_dft_status st = SPLIT_DFT_OK;
     if (e == hipSuccess) {
-        st = many_launch(plan, xr, xi, yr, yi, gr, gi, gxr, gxi, true, adj, s, &msg);
+        st = many_launch(plan, xr, xi, yr, yi, gr, gi, gxr, gxi, true, adj, workspace, workspace_bytes, s, &msg);
         const hipError_t e2 = hipStreamEndCapture(s, &graph);
         if (st == SPLIT_DFT_OK && e2 != hipSuccess)
             e = e2;
@@ -510,6 +619,7 @@ split_dft_status split_dft_many_graph(split_dft_many_t plan, const float* xr, co
     if (st != SPLIT_DFT_OK) {
         if (graph)
             (void)hipGraphDestroy(graph);
+        delete g;
         return fail(st, msg);
     }
     hipGraphExec_t exec = nullptr;
@@ -518,15 +628,24 @@ split_dft_status split_dft_many_graph(split_dft_many_t plan, const float* xr, co
     if (e != hipSuccess) {
         if (graph)
             (void)hipGraphDestroy(graph);
+        delete g;
         return fail(SPLIT_DFT_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
     }
-    auto* g = new (std::nothrow) split_dft_graph_s{graph, exec};
-    if (!g) {
-        (void)hipGraphExecDestroy(exec);
-        (void)hipGraphDestroy(graph);
-        return fail(SPLIT_DFT_ERR_OUT_OF_MEMORY, "host allocation of the graph");
+    g->graph = graph;
+    g->exec = exec;
+    {
+        // the graph's kernels use the plan's device data: hold a reference
+        // (a plan destroyed meanwhile would be gone from the live set)
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (live().count(plan) == 0) {
+            (void)hipGraphExecDestroy(exec);
+            (void)hipGraphDestroy(graph);
+            delete g;
+            return fail(SPLIT_DFT_ERR_INVALID_PLAN, "grouped plan destroyed during graph capture");
+        }
+        ++plan->refs;
+        live().insert(g);
     }
-    set_live(g, true);
     *out = g;
     return SPLIT_DFT_OK;
 }
@@ -545,12 +664,13 @@ split_dft_status split_dft_graph_destroy(split_dft_graph_t graph)
 {
     if (!graph)
         return SPLIT_DFT_OK;
-    if (!is_live(graph))
+    if (!take_live(graph))
         return fail(SPLIT_DFT_ERR_INVALID_PLAN, "graph is destroyed");
-    set_live(graph, false);
     hipError_t e = hipGraphExecDestroy(graph->exec);
     const hipError_t e2 = hipGraphDestroy(graph->graph);
+    split_dft_many_s* plan = graph->plan;
     delete graph;
+    release_many(plan);
     if (e == hipSuccess)
         e = e2;
     return e == hipSuccess ? SPLIT_DFT_OK : fail(SPLIT_DFT_ERR_HIP, hipGetErrorString(e));
@@ -560,16 +680,9 @@ split_dft_status split_dft_many_destroy(split_dft_many_t plan)
 {
     if (!plan)
         return SPLIT_DFT_OK;
-    if (!is_live(plan))
+    if (!take_live(plan))
         return fail(SPLIT_DFT_ERR_INVALID_PLAN, "grouped plan is destroyed");
-    set_live(plan, false);
-    int cur = 0;
-    const bool sw = hipGetDevice(&cur) == hipSuccess && cur != plan->device;
-    if (sw)
-        (void)hipSetDevice(plan->device);
-    free_many(plan);
-    if (sw)
-        (void)hipSetDevice(cur);
+    release_many(plan);
     return SPLIT_DFT_OK;
 }
 

@@ -269,10 +269,13 @@ __device__ __forceinline__ void run_stages(float (&vr)[C::E], float (&vi)[C::E],
     }
 }
 
-template <class C>
+// DUAL: the grid covers two directions over the same rows, the first
+// ceil(batch / TPW) workgroups the planes (xr, xi, yr, yi), the rest those of
+// d2 (a fused forward + adjoint); otherwise d2 is unused.
+template <class C, bool DUAL>
 __global__ void __launch_bounds__(C::THREADS) __attribute__((amdgpu_waves_per_eu(C::WPE)))
 split_fft_lds_kernel(const float* xr, const float* xi, float* yr, float* yi, const float2* __restrict__ tw,
-                     int64_t batch, const int64_t* __restrict__ rows)
+                     int64_t batch, const int64_t* __restrict__ rows, Dir2 d2)
 {
     constexpr int M = C::M, RB = C::RB, TPW = C::TPW;
     constexpr int N = C::N, E = C::E, LT = C::LT, T = C::T, NP = C::NP;
@@ -283,7 +286,18 @@ split_fft_lds_kernel(const float* xr, const float* xi, float* yr, float* yi, con
     const int tid = threadIdx.x;
     const int slot = tid >> LT;
     const int t = tid & (T - 1);
-    const int64_t b0 = static_cast<int64_t>(blockIdx.x) * TPW;
+    int64_t wg = blockIdx.x;
+    if constexpr (DUAL) {
+        const int64_t nb = (batch + TPW - 1) / TPW;
+        if (wg >= nb) {
+            wg -= nb;
+            xr = d2.xr;
+            xi = d2.xi;
+            yr = d2.yr;
+            yi = d2.yi;
+        }
+    }
+    const int64_t b0 = wg * TPW;
     const int64_t b = b0 + slot;
     const bool active = b < batch;
     // rows (one transform per workgroup only): element offset of each transform
@@ -451,11 +465,13 @@ __device__ __forceinline__ void pin_regs(float (&v)[E])
 // blocks blockIdx.x, blockIdx.x + gridDim.x, ...  The twiddles are staged in
 // LDS once per workgroup, and the 16-byte loads of the next block go into
 // registers right after the current block has left them, so that they are
-// in flight during the current block's passes and stores.
-template <class C>
+// in flight during the current block's passes and stores.  DUAL: blocks
+// ceil(batch / TPW) and up run on the planes of d2 (as in
+// split_fft_lds_kernel).
+template <class C, bool DUAL>
 __global__ void __launch_bounds__(C::THREADS) __attribute__((amdgpu_waves_per_eu(C::WPE)))
 split_fft_pf_kernel(const float* xr, const float* xi, float* yr, float* yi, const float2* __restrict__ tw,
-                    int64_t batch, const int64_t* __restrict__ rows)
+                    int64_t batch, const int64_t* __restrict__ rows, Dir2 d2)
 {
     constexpr int M = C::M, RB = C::RB, TPW = C::TPW;
     constexpr int N = C::N, E = C::E, LT = C::LT, T = C::T, NP = C::NP;
@@ -485,13 +501,21 @@ split_fft_pf_kernel(const float* xr, const float* xi, float* yr, float* yi, cons
         __syncthreads();
     }
 
-    const int64_t blocks = (batch + TPW - 1) / TPW;
+    const int64_t nb = (batch + TPW - 1) / TPW;  // blocks of one direction
+    const int64_t blocks = DUAL ? 2 * nb : nb;
+    // block of its own direction, and that direction's planes
+    auto local = [&](int64_t blk) { return (DUAL && blk >= nb) ? blk - nb : blk; };
+    auto src_r = [&](int64_t blk) { return (DUAL && blk >= nb) ? d2.xr : xr; };
+    auto src_i = [&](int64_t blk) { return (DUAL && blk >= nb) ? d2.xi : xi; };
     // rows (one transform per workgroup only): element offset of each transform
     const bool indirect = TPW == 1 && rows != nullptr;
-    auto group_base = [&](int64_t blk) { return indirect ? rows[blk] : (blk * TPW + gslot0) * N; };
+    auto group_base = [&](int64_t blk) {
+        const int64_t lb = local(blk);
+        return indirect ? rows[lb] : (lb * TPW + gslot0) * N;
+    };
     // floats of the sync group's rows that exist in block blk
     auto group_valid = [&](int64_t blk) {
-        const int64_t rows_left = batch - (blk * TPW + gslot0);
+        const int64_t rows_left = batch - (local(blk) * TPW + gslot0);
         return static_cast<int>(rows_left < GSLOTS ? (rows_left > 0 ? rows_left : 0) : GSLOTS) * N;
     };
 
@@ -504,8 +528,8 @@ split_fft_pf_kernel(const float* xr, const float* xi, float* yr, float* yi, cons
     if (blk < blocks) {
         const int valid = group_valid(blk);
         const int64_t base = group_base(blk);
-        load_rows<C, GT>(pr, xr, base, valid, gtid);
-        load_rows<C, GT>(pi, xi, base, valid, gtid);
+        load_rows<C, GT>(pr, src_r(blk), base, valid, gtid);
+        load_rows<C, GT>(pi, src_i(blk), base, valid, gtid);
         if constexpr (TPW == 1) {
             ahead[0] = base;
             if (blk + gridDim.x < blocks)
@@ -515,6 +539,8 @@ split_fft_pf_kernel(const float* xr, const float* xi, float* yr, float* yi, cons
     for (; blk < blocks; blk += gridDim.x) {
         const int valid = group_valid(blk);
         const int64_t base = TPW == 1 ? ahead[0] : group_base(blk);
+        float* dst_r = (DUAL && blk >= nb) ? d2.yr : yr;
+        float* dst_i = (DUAL && blk >= nb) ? d2.yi : yi;
         // the position and twiddle addresses below depend only on t; an
         // opaque copy per iteration keeps the compiler from hoisting all of
         // them out of the loop into registers that the prefetch needs
@@ -549,8 +575,8 @@ split_fft_pf_kernel(const float* xr, const float* xi, float* yr, float* yi, cons
         if (nblk < blocks) {
             const int nvalid = group_valid(nblk);
             const int64_t nbase = TPW == 1 ? ahead[1] : group_base(nblk);
-            load_rows<C, GT>(pr, xr, nbase, nvalid, gtid);
-            load_rows<C, GT>(pi, xi, nbase, nvalid, gtid);
+            load_rows<C, GT>(pr, src_r(nblk), nbase, nvalid, gtid);
+            load_rows<C, GT>(pi, src_i(nblk), nbase, nvalid, gtid);
         }
         if constexpr (TPW == 1) {
             ahead[0] = ahead[1];
@@ -563,25 +589,25 @@ split_fft_pf_kernel(const float* xr, const float* xi, float* yr, float* yi, cons
             if constexpr (C::SPLIT) {
                 regs_to_natural<C>(vr, lr, t);
                 xsync<T>();
-                stage_out<C, GT>(yr, gr, base, valid, gtid);
+                stage_out<C, GT>(dst_r, gr, base, valid, gtid);
                 xsync<T>();
                 regs_to_natural<C>(vi, lr, t);
                 xsync<T>();
-                stage_out<C, GT>(yi, gr, base, valid, gtid);
+                stage_out<C, GT>(dst_i, gr, base, valid, gtid);
             } else {
                 regs_to_natural<C>(vr, lr, t);
                 regs_to_natural<C>(vi, li, t);
                 xsync<T>();
-                stage_out<C, GT>(yr, gr, base, valid, gtid);
-                stage_out<C, GT>(yi, gi, base, valid, gtid);
+                stage_out<C, GT>(dst_r, gr, base, valid, gtid);
+                stage_out<C, GT>(dst_i, gi, base, valid, gtid);
             }
             // the next block's put_rows reuses the slots
             xsync<T>();
         } else {
             // the last exchange ended with a sync, so the slots are free
-            const int64_t b = blk * TPW + slot;
+            const int64_t b = local(blk) * TPW + slot;
             if (b < batch)
-                store_last<C>(yr, yi, indirect ? base : b * N, vr, vi, t);
+                store_last<C>(dst_r, dst_i, indirect ? base : b * N, vr, vi, t);
         }
     }
 }
@@ -599,7 +625,7 @@ __global__ void __launch_bounds__(256) split_fft_len1_kernel(const float* xr, co
 }
 
 hipError_t launch_len1(const float* xr, const float* xi, float* yr, float* yi, const float2*, int64_t batch,
-                       const int64_t* rows, hipStream_t stream)
+                       const int64_t* rows, hipStream_t stream, const Dir2* second)
 {
     if (rows)
         return hipErrorInvalidValue;
@@ -608,31 +634,36 @@ hipError_t launch_len1(const float* xr, const float* xi, float* yr, float* yi, c
         return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(split_fft_len1_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, xr, xi, yr,
                        yi, batch);
+    if (second)
+        hipLaunchKernelGGL(split_fft_len1_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream,
+                           second->xr, second->xi, second->yr, second->yi, batch);
     return hipGetLastError();
 }
 
 template <class C>
 hipError_t launch_lds(const float* xr, const float* xi, float* yr, float* yi, const float2* tw, int64_t batch,
-                      const int64_t* rows, hipStream_t stream)
+                      const int64_t* rows, hipStream_t stream, const Dir2* second)
 {
     if (rows && C::TPW != 1)
         return hipErrorInvalidValue;
     const int64_t blocks = (batch + C::TPW - 1) / C::TPW;
-    if (blocks > INT_MAX)
+    if (blocks > INT_MAX / 2)
         return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(split_fft_lds_kernel<C>, dim3(static_cast<unsigned>(blocks)), dim3(C::THREADS), 0, stream,
-                       xr, xi, yr, yi, tw, batch, rows);
+    if (second)
+        hipLaunchKernelGGL((split_fft_lds_kernel<C, true>), dim3(static_cast<unsigned>(2 * blocks)),
+                           dim3(C::THREADS), 0, stream, xr, xi, yr, yi, tw, batch, rows, *second);
+    else
+        hipLaunchKernelGGL((split_fft_lds_kernel<C, false>), dim3(static_cast<unsigned>(blocks)), dim3(C::THREADS),
+                           0, stream, xr, xi, yr, yi, tw, batch, rows, Dir2{});
     return hipGetLastError();
 }
 
 // Workgroups of the persistent form: as many as can be resident at once.
-template <class C>
-hipError_t launch_pf(const float* xr, const float* xi, float* yr, float* yi, const float2* tw, int64_t batch,
-                     const int64_t* rows, hipStream_t stream)
+template <class C, bool DUAL>
+hipError_t launch_pf_dir(const float* xr, const float* xi, float* yr, float* yi, const float2* tw, int64_t batch,
+                         const int64_t* rows, hipStream_t stream, const Dir2& second)
 {
-    if (rows && C::TPW != 1)
-        return hipErrorInvalidValue;
-    const int64_t blocks = (batch + C::TPW - 1) / C::TPW;
+    const int64_t blocks = (batch + C::TPW - 1) / C::TPW * (DUAL ? 2 : 1);
     // resident workgroups per device, looked up once (launches are frequent)
     static std::atomic<int> resident_of[kMaxDevices];
     int dev = 0;
@@ -644,7 +675,7 @@ hipError_t launch_pf(const float* xr, const float* xi, float* yr, float* yi, con
         int cus = 0, per_cu = 0;
         e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e == hipSuccess)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, split_fft_pf_kernel<C>, C::THREADS, 0);
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, split_fft_pf_kernel<C, DUAL>, C::THREADS, 0);
         if (e != hipSuccess)
             return e;
         if (per_cu < 1 || cus < 1)
@@ -654,9 +685,20 @@ hipError_t launch_pf(const float* xr, const float* xi, float* yr, float* yi, con
             resident_of[dev].store(resident, std::memory_order_relaxed);
     }
     const int64_t grid = blocks < resident ? blocks : resident;
-    hipLaunchKernelGGL(split_fft_pf_kernel<C>, dim3(static_cast<unsigned>(grid)), dim3(C::THREADS), 0, stream, xr,
-                       xi, yr, yi, tw, batch, rows);
+    hipLaunchKernelGGL((split_fft_pf_kernel<C, DUAL>), dim3(static_cast<unsigned>(grid)), dim3(C::THREADS), 0,
+                       stream, xr, xi, yr, yi, tw, batch, rows, second);
     return hipGetLastError();
+}
+
+template <class C>
+hipError_t launch_pf(const float* xr, const float* xi, float* yr, float* yi, const float2* tw, int64_t batch,
+                     const int64_t* rows, hipStream_t stream, const Dir2* second)
+{
+    if (rows && C::TPW != 1)
+        return hipErrorInvalidValue;
+    if (second)
+        return launch_pf_dir<C, true>(xr, xi, yr, yi, tw, batch, rows, stream, *second);
+    return launch_pf_dir<C, false>(xr, xi, yr, yi, tw, batch, rows, stream, Dir2{});
 }
 
 template <class C>

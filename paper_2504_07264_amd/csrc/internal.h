@@ -11,6 +11,15 @@ namespace splitdft {
 // The message split_dft_last_error() returns on this thread.
 void set_last_error(const std::string& msg);
 
+// Planes of a second direction run in the same launch as the first (a fused
+// forward + adjoint: the adjoint's planes are passed already exchanged).
+struct Dir2 {
+    const float* xr;
+    const float* xi;
+    float* yr;
+    float* yi;
+};
+
 // One compiled single-pass kernel: transforms of length 2^m, 2^rb elements per
 // thread, tpw transforms per workgroup, plus data-movement options.
 struct Variant {
@@ -25,9 +34,11 @@ struct Variant {
     int wpe;      // occupancy hint (minimum waves per SIMD)
     int f4io;     // 16-byte global I/O staged through LDS: 0 no, 1 both ways, 2 loads
     // rows: NULL for a contiguous [batch][n] layout, else the element offset
-    // of each transform (accepted when rows_ok)
+    // of each transform (accepted when rows_ok); second: NULL, or the planes
+    // of a second direction over the same rows, run in the same launch
     hipError_t (*launch)(const float* xr, const float* xi, float* yr, float* yi,
-                         const float2* tw, int64_t batch, const int64_t* rows, hipStream_t stream);
+                         const float2* tw, int64_t batch, const int64_t* rows, hipStream_t stream,
+                         const Dir2* second);
     bool pf = false;       // persistent workgroups, next block's loads prefetched
     bool rows_ok = false;  // takes per-transform offsets (one transform per workgroup)
 };

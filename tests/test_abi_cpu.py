@@ -56,6 +56,8 @@ def test_plan_rejects_bad_batch(L, batch):
 def test_plan_rejects_unknown_flags(L):
     assert _plan(L, 16, 4, 0x7)[0] == 6
     assert _plan(L, 16, 4, 1 << 20)[0] == 6
+    assert _plan(L, 16, 4, 1 << 31)[0] == 6
+    assert _plan(L, 16, 4, binding.CALLER_WORKSPACE | (1 << 29))[0] == 6
     # a schedule selector beyond the compiled ones
     assert _plan(L, 16, 4, binding.variant_flag(200))[0] == 6
 
@@ -89,6 +91,8 @@ def test_calls_with_invalid_plan(L):
     assert L.split_dft_exec(None, buf, buf, buf, buf, None) == 9
     assert L.split_dft_exec(bogus, buf, buf, buf, buf, None) == 9
     assert L.split_dft_adjoint(bogus, buf, buf, buf, buf, None) == 9
+    assert L.split_dft_exec_adjoint(bogus, buf, buf, buf, buf, buf, buf, buf, buf, None) == 9
+    assert L.split_dft_exec_adjoint_ws(bogus, buf, buf, buf, buf, buf, buf, buf, buf, buf, 1 << 20, None) == 9
     assert L.split_dft_destroy(bogus) == 9
     assert L.split_dft_destroy(None) == 0
     assert L.split_dft_plan_info(bogus, None, None, None, None, None) == 9
@@ -138,13 +142,22 @@ def test_many_plan_validates_before_any_hip_call(L):
     assert L.split_dft_many_plan(ctypes.byref(h), a.ctypes.data, 0, 0) == 2
     assert L.split_dft_many_plan(ctypes.byref(h), a.ctypes.data, 2, 1) == 6
     assert L.split_dft_many_plan(ctypes.byref(h), a.ctypes.data, 2, 9 << 8) == 6
-    assert L.split_dft_many_plan(ctypes.byref(h), a.ctypes.data, 2, 1 << 30) == 6
+    assert L.split_dft_many_plan(ctypes.byref(h), a.ctypes.data, 2, 1 << 31) == 6
     assert L.split_dft_many_plan(ctypes.byref(h), a.ctypes.data, 2, 9 << 25) == 6   # threshold below 2^10
     assert L.split_dft_many_plan(ctypes.byref(h), a.ctypes.data, 2, 18 << 25) == 6  # above 2^17
     assert L.split_dft_many_plan(None, a.ctypes.data, 2, 0) == 3
     assert L.split_dft_many_plan(ctypes.byref(h), None, 2, 0) == 3
     bogus = ctypes.c_void_p(0x1000)
     assert L.split_dft_many_exec(bogus, None, None, None, None, None) == 9
+    buf = ctypes.c_void_p(0x100000)
+    assert L.split_dft_many_exec_ws(bogus, buf, buf, buf, buf, buf, 1 << 20, None) == 9
+    assert L.split_dft_many_adjoint_ws(bogus, buf, buf, buf, buf, buf, 1 << 20, None) == 9
+    assert L.split_dft_many_exec_adjoint_ws(bogus, buf, buf, buf, buf, buf, buf, buf, buf, buf, 1 << 20,
+                                            None) == 9
+    g = ctypes.c_void_p()
+    assert L.split_dft_many_graph_ws(bogus, buf, buf, buf, buf, None, None, None, None, buf, 1 << 20,
+                                     ctypes.byref(g)) == 9
+    assert L.split_dft_many_workspace_bytes(None) == 0 and L.split_dft_many_workspace_bytes(bogus) == 0
     assert L.split_dft_graph_launch(bogus, None) == 9
     assert L.split_dft_many_destroy(None) == 0 and L.split_dft_graph_destroy(None) == 0
 

@@ -386,7 +386,7 @@ def test_two_pass_chunks_and_caller_workspace():
     xr, xi = inputs.draw_planes(n, batch, "normal", 13)
     mr, mi = oracle.split_fft_f32(xr.numpy(), xi.numpy())
     say("  two-pass n=%d batch=%d" % (n, batch))
-    with Plan(n, batch) as p:
+    with Plan(n, batch, own_workspace=True) as p:
         ws = p.workspace_bytes()
         assert 0 < ws <= (256 << 20)
         assert ws < 2 * 4 * n * batch  # chunked
@@ -422,6 +422,19 @@ def test_two_pass_chunks_and_caller_workspace():
                                    w.data_ptr() + 4, ws, s) == 4
         assert L.split_dft_exec_ws(p.handle, br.data_ptr(), bi.data_ptr(), yr.data_ptr(), yi.data_ptr(),
                                    yr.data_ptr(), ws, s) == 5
+    # a plan without a workspace of its own: NULL is an error, the binding
+    # allocates one per call through torch
+    with Plan(n, batch) as p:
+        assert p.workspace_bytes() > 0
+        L = binding.lib()
+        s = torch.cuda.current_stream().cuda_stream
+        br, bi = xr.cuda(), xi.cuda()
+        yr, yi = torch.empty_like(br), torch.empty_like(bi)
+        assert L.split_dft_exec(p.handle, br.data_ptr(), bi.data_ptr(), yr.data_ptr(), yi.data_ptr(), s) == 3
+        assert b"SPLIT_DFT_CALLER_WORKSPACE" in L.split_dft_last_error()
+        yr, yi = p.exec(br, bi)
+        torch.cuda.synchronize()
+        assert_bit_exact(to_np(yr), to_np(yi), mr, mi)
 
 
 def test_two_pass_calls_overlap_on_streams_with_own_workspaces():
