@@ -37,7 +37,7 @@ MAX_LOG2N = 16
 
 EXPORTED = (
     "split_dft_plan", "split_dft_exec", "split_dft_adjoint", "split_dft_exec_ws", "split_dft_adjoint_ws",
-    "split_dft_exec_adjoint", "split_dft_exec_adjoint_ws",
+    "split_dft_exec_adjoint", "split_dft_exec_adjoint_ws", "split_dft_exec_noalloc",
     "split_dft_destroy",
     "split_dft_workspace_bytes", "split_dft_plan_info", "split_dft_plan_describe", "split_dft_twiddle_table",
     "split_dft_status_string", "split_dft_last_error",
@@ -71,7 +71,7 @@ def lib() -> ctypes.CDLL:
         vp, i64, u32, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int
         L.split_dft_plan.argtypes = [ctypes.POINTER(vp), i64, i64, u32]
         L.split_dft_plan.restype = ci
-        for name in ("split_dft_exec", "split_dft_adjoint"):
+        for name in ("split_dft_exec", "split_dft_adjoint", "split_dft_exec_noalloc"):
             fn = getattr(L, name)
             fn.argtypes = [vp, vp, vp, vp, vp, vp]
             fn.restype = ci
@@ -309,6 +309,20 @@ class Plan:
                   (xr.data_ptr(), xi.data_ptr(), yr.data_ptr(), yi.data_ptr(), gr.data_ptr(), gi.data_ptr(),
                    gxr.data_ptr(), gxi.data_ptr()), workspace, xr)
         return yr, yi, gxr, gxi
+
+    def exec_noalloc(self, xr, xi, yr, yi):
+        """Forward transform into the given outputs through the library's
+        static scratch array: the call allocates nothing (for code under
+        graph capture).  Calls that overlap in time on one GPU race on that
+        array."""
+        yr, yi = self._planes(xr, xi, yr, yi, ("input real", "input imag", "output real", "output imag"))
+        args = (self._h, xr.data_ptr(), xi.data_ptr(), yr.data_ptr(), yi.data_ptr(), _stream_handle(self._index))
+        if torch.cuda.current_device() == self._index:
+            check(lib().split_dft_exec_noalloc(*args))
+        else:
+            with torch.cuda.device(self._index):
+                check(lib().split_dft_exec_noalloc(*args))
+        return yr, yi
 
     def close(self) -> None:
         h, self._h = getattr(self, "_h", None), None

@@ -19,7 +19,7 @@ BUILD_DIR = os.path.join(PKG, "_build")
 LIB_PATH = os.path.join(PKG, "libsplitdft.so")
 
 SOURCES = ["fft_lds.hip", "fft_tile.hip", "fft_many.hip", "fft_mfma.hip", "twiddle.cpp", "mfma_tables.cpp",
-           "api.cpp", "api_many.cpp"]
+           "api.cpp", "api_many.cpp", "noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

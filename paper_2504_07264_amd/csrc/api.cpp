@@ -134,11 +134,10 @@ struct Io {
     float* yi;
 };
 
-// One or two directions (dir[1].xr == NULL: one) on the caller's stream.  A
-// second direction runs in the same launch as the first where the schedule
-// allows (single-pass FP32), else after it; its arrays may not overlap the
-// first direction's.
-split_dft_status run(split_dft_plan_t p, const Io* dir, int ndir, void* ws, size_t ws_bytes, void* stream)
+// Arguments of one or two directions (dir[1].xr == NULL: one); makes no HIP
+// call.  A second direction may run in the same launch as the first, so its
+// arrays may not overlap the first direction's.
+split_dft_status validate_call(split_dft_plan_t p, const Io* dir, int ndir)
 {
     if (!p || !plan_is_live(p))
         return fail(SPLIT_DFT_ERR_INVALID_PLAN, "plan is NULL, destroyed or not created by split_dft_plan");
@@ -157,38 +156,31 @@ split_dft_status run(split_dft_plan_t p, const Io* dir, int ndir, void* ws, size
                     if (ranges_overlap(out, bytes, other, bytes))
                         return fail(SPLIT_DFT_ERR_ALIASING, "forward and adjoint arrays overlap");
     }
-    float* w = static_cast<float*>(ws);
-    if (p->two) {
-        if (!w) {
-            w = p->d_ws;
-            if (!w)
-                return fail(SPLIT_DFT_ERR_NULL_POINTER,
-                            "the plan was created with SPLIT_DFT_CALLER_WORKSPACE: pass a workspace of "
-                            "split_dft_workspace_bytes(plan) = " + std::to_string(p->ws_bytes) + " bytes");
-        } else {
-            if (ws_bytes < p->ws_bytes)
-                return fail(SPLIT_DFT_ERR_INVALID_BATCH, "workspace smaller than split_dft_workspace_bytes");
-            if (reinterpret_cast<uintptr_t>(w) % 16 != 0)
-                return fail(SPLIT_DFT_ERR_MISALIGNED, "workspace must be 16-byte aligned");
-            for (int k = 0; k < ndir; ++k)
-                for (const void* q : {static_cast<const void*>(dir[k].xr), static_cast<const void*>(dir[k].xi),
-                                      static_cast<const void*>(dir[k].yr), static_cast<const void*>(dir[k].yi)})
-                    if (ranges_overlap(w, p->ws_bytes, q, bytes))
-                        return fail(SPLIT_DFT_ERR_ALIASING, "workspace overlaps a data array");
-        }
-    }
-    // the plan's tables live on the device it was created on
+    return SPLIT_DFT_OK;
+}
+
+// The plan's tables live on the device it was created on.
+split_dft_status check_device(const split_dft_plan_s* p)
+{
     int cur = -1;
     if (hipGetDevice(&cur) != hipSuccess || cur != p->device)
         return fail(SPLIT_DFT_ERR_INVALID_PLAN, "the plan belongs to HIP device " + std::to_string(p->device) +
                                                     ", the current device is " + std::to_string(cur));
-    const hipStream_t st = static_cast<hipStream_t>(stream);
+    return SPLIT_DFT_OK;
+}
+
+// Launch validated directions on the stream.  Two-pass plans go through the
+// workspace w in chunks of `chunk` transforms (w holds 2 * chunk * n floats);
+// single-pass FP32 schedules run a second direction in the same launch.
+split_dft_status launch_dirs(const split_dft_plan_s* p, const Io* dir, int ndir, float* w, int64_t chunk,
+                             hipStream_t st)
+{
     if (p->two) {
         float* wr = w;
-        float* wi = w + p->chunk * p->n;
+        float* wi = w + chunk * p->n;
         for (int k = 0; k < ndir; ++k)
-            for (int64_t s0 = 0; s0 < p->batch; s0 += p->chunk) {
-                const int64_t c = p->batch - s0 < p->chunk ? p->batch - s0 : p->chunk;
+            for (int64_t s0 = 0; s0 < p->batch; s0 += chunk) {
+                const int64_t c = p->batch - s0 < chunk ? p->batch - s0 : chunk;
                 const int64_t off = s0 * p->n;
                 hipError_t e = p->two->pass1(dir[k].xr + off, dir[k].xi + off, wr, wi, p->d_tw, c, nullptr, st);
                 if (e == hipSuccess)
@@ -217,12 +209,82 @@ split_dft_status run(split_dft_plan_t p, const Io* dir, int ndir, void* ws, size
     return SPLIT_DFT_OK;
 }
 
+// One or two directions on the caller's stream, through the caller's
+// workspace ws (NULL: the plan's own).
+split_dft_status run(split_dft_plan_t p, const Io* dir, int ndir, void* ws, size_t ws_bytes, void* stream)
+{
+    split_dft_status vs = validate_call(p, dir, ndir);
+    if (vs != SPLIT_DFT_OK)
+        return vs;
+    const size_t bytes = static_cast<size_t>(p->n) * static_cast<size_t>(p->batch) * sizeof(float);
+    float* w = static_cast<float*>(ws);
+    if (p->two) {
+        if (!w) {
+            w = p->d_ws;
+            if (!w)
+                return fail(SPLIT_DFT_ERR_NULL_POINTER,
+                            "the plan was created with SPLIT_DFT_CALLER_WORKSPACE: pass a workspace of "
+                            "split_dft_workspace_bytes(plan) = " + std::to_string(p->ws_bytes) + " bytes");
+        } else {
+            if (ws_bytes < p->ws_bytes)
+                return fail(SPLIT_DFT_ERR_INVALID_BATCH, "workspace smaller than split_dft_workspace_bytes");
+            if (reinterpret_cast<uintptr_t>(w) % 16 != 0)
+                return fail(SPLIT_DFT_ERR_MISALIGNED, "workspace must be 16-byte aligned");
+            for (int k = 0; k < ndir; ++k)
+                for (const void* q : {static_cast<const void*>(dir[k].xr), static_cast<const void*>(dir[k].xi),
+                                      static_cast<const void*>(dir[k].yr), static_cast<const void*>(dir[k].yi)})
+                    if (ranges_overlap(w, p->ws_bytes, q, bytes))
+                        return fail(SPLIT_DFT_ERR_ALIASING, "workspace overlaps a data array");
+        }
+    }
+    vs = check_device(p);
+    if (vs != SPLIT_DFT_OK)
+        return vs;
+    return launch_dirs(p, dir, ndir, w, p->chunk, static_cast<hipStream_t>(stream));
+}
+
 // C gr - S gi = imaginary part and S gr + C gi = real part of the forward
 // transform of (gi, gr): the adjoint is the forward kernel with both plane
 // pairs exchanged.
 Io adjoint_io(const float* gr, const float* gi, float* gxr, float* gxi) { return Io{gi, gr, gxi, gxr}; }
 
 }  // namespace
+
+namespace splitdft {
+
+split_dft_status exec_in_scratch(split_dft_plan_t p, const float* xr, const float* xi, float* yr, float* yi,
+                                 void* stream, ScratchLookup lookup)
+{
+    const Io io[2] = {{xr, xi, yr, yi}, {}};
+    split_dft_status vs = validate_call(p, io, 1);
+    if (vs != SPLIT_DFT_OK)
+        return vs;
+    vs = check_device(p);
+    if (vs != SPLIT_DFT_OK)
+        return vs;
+    float* w = nullptr;
+    int64_t chunk = p->chunk;
+    if (p->two) {
+        size_t cap = 0;
+        const hipError_t e = lookup(p->device, &w, &cap);
+        if (e != hipSuccess)
+            return fail_hip(e, "address of the static scratch array");
+        const int64_t per = p->n * 2 * static_cast<int64_t>(sizeof(float));
+        const int64_t fit = static_cast<int64_t>(cap) / per;
+        if (fit < 1)
+            return fail(SPLIT_DFT_ERR_UNSUPPORTED, "one transform's intermediate (" + std::to_string(per) +
+                                                       " bytes) exceeds the static scratch (" +
+                                                       std::to_string(cap) + " bytes)");
+        if (fit < chunk) {
+            // equal chunks of at most `fit` transforms
+            const int64_t nchunks = (p->batch + fit - 1) / fit;
+            chunk = (p->batch + nchunks - 1) / nchunks;
+        }
+    }
+    return launch_dirs(p, io, 1, w, chunk, static_cast<hipStream_t>(stream));
+}
+
+}  // namespace splitdft
 
 extern "C" {
 
@@ -337,6 +399,8 @@ split_dft_status split_dft_plan(split_dft_plan_t* out, int64_t n, int64_t batch,
                                             : fail_hip(e, "hipMalloc of the workspace");
         }
     }
+    if (two)
+        splitdft::prepare_noalloc_scratch(dev);  // set-up: the no-allocation entry point's array
     auto* p = new (std::nothrow)
         split_dft_plan_s{n, batch, m, flags, dev, d_tw, v, mode, d_mfma, two, chunk, d_ws, ws_bytes};
     if (!p) {

@@ -6,6 +6,8 @@
 
 #include <string>
 
+#include "../../include/split_dft.h"
+
 namespace splitdft {
 
 // The message split_dft_last_error() returns on this thread.
@@ -148,5 +150,17 @@ void build_tw256(float* cs);
 // Launch the matrix-core kernel (only length 2^8 is supported).
 hipError_t launch_mfma(int mode, int m, const float* xr, const float* xi, float* yr, float* yi, const float* consts,
                        const float2* tw256, int64_t batch, hipStream_t stream);
+
+// ---- no-allocation entry point ------------------------------------------
+// Device address and size of the static scratch array on `device` (which must
+// be the current device); looked up once per device.
+using ScratchLookup = hipError_t (*)(int device, float** ptr, size_t* bytes);
+// Set-up: look the array up on the current device (errors are reported by the
+// entry point's own lookup).
+void prepare_noalloc_scratch(int device);
+// split_dft_exec with two-pass intermediates in the scratch array `lookup`
+// returns, in chunks that fit it; validates before any HIP call.
+split_dft_status exec_in_scratch(split_dft_plan_t p, const float* xr, const float* xi, float* yr, float* yi,
+                                 void* stream, ScratchLookup lookup);
 
 }  // namespace splitdft

@@ -91,6 +91,8 @@ def test_calls_with_invalid_plan(L):
     assert L.split_dft_exec(None, buf, buf, buf, buf, None) == 9
     assert L.split_dft_exec(bogus, buf, buf, buf, buf, None) == 9
     assert L.split_dft_adjoint(bogus, buf, buf, buf, buf, None) == 9
+    assert L.split_dft_exec_noalloc(None, buf, buf, buf, buf, None) == 9
+    assert L.split_dft_exec_noalloc(bogus, buf, buf, buf, buf, None) == 9
     assert L.split_dft_exec_adjoint(bogus, buf, buf, buf, buf, buf, buf, buf, buf, None) == 9
     assert L.split_dft_exec_adjoint_ws(bogus, buf, buf, buf, buf, buf, buf, buf, buf, buf, 1 << 20, None) == 9
     assert L.split_dft_destroy(bogus) == 9
