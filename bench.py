@@ -5,18 +5,25 @@ One step = the whole path on one batch: the forward transform (eq. 5 via the
 factorisation of eq. 6) of 16384 rows of length 1024, followed by the adjoint
 (backward) transform of an upstream gradient of the same shape.  Inputs are
 resident in HBM before timing starts; buffer sets rotate (>= 1 GiB in total)
-so the 256 MB Infinity Cache cannot serve repeats.
+so the 256 MB Infinity Cache cannot serve repeats.  The kernel schedule is
+the autotuner's choice, timed on this device before the timed region.
 
 Prints ONE JSON line (rank 0):
   value      algorithmic GB/s of the step (16 B per complex point per
-             direction: 8 B read + 8 B written, FP32 planar)
+             direction: 8 B read + 8 B written, FP32 planar), from the host
+             clock around the timed steps
   roofline   the dominant kernel (the length-1024 kernel, which both the
              forward and the adjoint launch): algorithmic bytes per launch /
              its mean time per launch, from HIP events recorded on the launch
              stream at both ends of the timed region (which holds nothing
              else), against 8 TB/s
+  kernel_us_per_launch  median, p10 and p90 of >= 100 launches, each between
+             two HIP events (a second timed region)
   cpu_baseline  the CPU oracle (FP64 factorised transform, OpenMP over rows)
              on the same step, timed on this host's cores
+Side reports: the fused forward + adjoint launch, matrix cores against FP32
+(time and error per mode), the copy ceiling, DIF, N=4096 forward + adjoint,
+the two-pass lengths and the ragged batch (default and tuned schedules).
 """
 from __future__ import annotations
 
@@ -37,6 +44,37 @@ HBM_PEAK_GBS = 8000.0
 N, BATCH = 1024, 16384
 ROTATE_SETS = 4
 PREWARM_S = 1.0
+MIN_ITERS = 100  # timed iterations per side measurement
+
+
+def stats_us(us):
+    """Median, p10, p90 and mean of a list of microsecond timings (n: how
+    many timed groups)."""
+    t = sorted(us)
+
+    def q(f):
+        return t[min(len(t) - 1, max(0, int(round(f * (len(t) - 1)))))]
+
+    return {"median": round(q(0.5), 2), "p10": round(q(0.1), 2), "p90": round(q(0.9), 2),
+            "mean": round(sum(t) / len(t), 2), "n": len(t)}
+
+
+def event_times(fn, iters, stream, group: int = 4):
+    """Run fn(k) for k < iters * group, back to back, with a HIP event recorded
+    on `stream` before the first call and after every `group` calls; returns
+    the microseconds per call of each group (an event between every call
+    would keep consecutive kernels from overlapping and add its own time)."""
+    import torch
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(iters + 1)]
+    ev[0].record(stream)
+    for j in range(iters):
+        for k in range(j * group, (j + 1) * group):
+            fn(k)
+        ev[j + 1].record(stream)
+    torch.cuda.synchronize()
+    return [ev[j].elapsed_time(ev[j + 1]) * 1e3 / group for j in range(iters)]
+
 
 # HBM traffic of the forward length-1024 kernel: rocprofv3 FETCH_SIZE and
 # WRITE_SIZE per dispatch, scaled by what the same counters read for a plain
@@ -215,11 +253,33 @@ def counters_run(workload: str = "n1024", reps: int = 5):
 MFMA_PER_TRANSFORM = {"bf16x2": 2 * 2 * 3, "fp16x2": 2 * 2 * 3, "bf16x3": 2 * 2 * 6}
 MFMA_FLOPS = 2 * 16 * 16 * 32
 MFMA_PEAK_TFLOPS = 2500.0  # dense bf16 / fp16
+ERROR_ROWS = 512  # sampled rows for the error of each precision mode
 
 
-def mfma_vs_fp32(steps: int = 50, sets: int = 4):
+def tol(n: int) -> float:
+    """The FP32 accuracy bound: relative L2 error per transform <= 2e-7 log2 N + 1e-7."""
+    return 2e-7 * math.log2(n) + 1e-7
+
+
+def rel_error_fp64(xr, xi, yr, yi, rows):
+    """Relative L2 error per row (both planes together) of (yr, yi) against
+    numpy's FP64 FFT of the same FP32 inputs, over the sampled rows: the
+    forward DFT of eq. (1), whose real and imaginary parts are eq. (5)."""
+    import numpy as np
+
+    x = xr[rows].astype(np.float64) + 1j * xi[rows].astype(np.float64)
+    ref = np.fft.fft(x, axis=1)
+    got = yr[rows].astype(np.float64) + 1j * yi[rows].astype(np.float64)
+    err = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    return {"max": float("%.3g" % err.max()), "median": float("%.3g" % np.median(err)), "rows": int(len(rows))}
+
+
+def mfma_vs_fp32(iters: int = MIN_ITERS, sets: int = 4):
     """Forward N=256 x 65536 (uniform[-1, 1], seed 3) in FP32 and in the three
-    matrix-core split-precision modes: mean launch time from HIP events."""
+    matrix-core split-precision modes: launch time (median, p10, p90 of HIP
+    event intervals) and the relative L2 error of sampled rows against an FP64
+    FFT (outside the timed region)."""
+    import numpy as np
     import torch
 
     from paper_2504_07264_amd import Plan, binding, inputs
@@ -230,35 +290,54 @@ def mfma_vs_fp32(steps: int = 50, sets: int = 4):
     bufs = [(xr.to(dev), xi.to(dev), torch.empty_like(xr, device=dev), torch.empty_like(xi, device=dev))
             for _ in range(sets)]
     stream = torch.cuda.current_stream(dev)
-    out = {"workload": "split_fft_n256_b65536_uniform forward", "n": w.n, "batch": w.batch}
+    rows = np.sort(np.random.default_rng(7).choice(w.batch, ERROR_ROWS, replace=False))
+    xr_np, xi_np = xr.numpy(), xi.numpy()
+    out = {"workload": "split_fft_n256_b65536_uniform forward", "n": w.n, "batch": w.batch,
+           "error": "relative L2 per transform against an FP64 FFT, %d sampled rows; FP32 bound %.2e"
+                    % (ERROR_ROWS, tol(w.n))}
     nbytes = 16 * w.n * w.batch
     for name in ("fp32", "bf16x2", "fp16x2", "bf16x3"):
         with Plan(w.n, w.batch, binding.PRECISIONS[name]) as plan:
             for k in range(5):
-                a, b, c, d = bufs[k % sets]
-                plan.exec(a, b, c, d)
-            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                  for _ in range(steps)]
-            for k in range(steps):
-                a, b, c, d = bufs[k % sets]
-                ev[k][0].record(stream)
-                plan.exec(a, b, c, d)
-                ev[k][1].record(stream)
+                plan.exec(*bufs[k % sets])
+            us = stats_us(event_times(lambda k: plan.exec(*bufs[k % sets]), iters, stream))
+            a, b, c, d = bufs[0]
+            plan.exec(a, b, c, d)
             torch.cuda.synchronize()
-            us = sum(x.elapsed_time(y) for x, y in ev) / steps * 1e3
-            rec = {"us": round(us, 2), "GBps": round(nbytes / us / 1e3, 1), "schedule": plan.describe()}
+            err = rel_error_fp64(xr_np, xi_np, c.cpu().numpy(), d.cpu().numpy(), rows)
+            err["within_fp32_bound"] = err["max"] <= tol(w.n)
+            rec = {"us": us, "GBps": round(nbytes / us["median"] / 1e3, 1), "schedule": plan.describe(),
+                   "rel_l2_error": err}
             if name in MFMA_PER_TRANSFORM:
-                tflops = MFMA_PER_TRANSFORM[name] * MFMA_FLOPS * w.batch / us / 1e6
+                tflops = MFMA_PER_TRANSFORM[name] * MFMA_FLOPS * w.batch / us["median"] / 1e6
                 rec["mfma_tflops"] = round(tflops, 1)
                 rec["mfma_utilisation"] = round(tflops / MFMA_PEAK_TFLOPS, 4)
             out[name] = rec
+    for name in ("bf16x2", "fp16x2", "bf16x3"):
+        out[name]["time_vs_fp32"] = round(out[name]["us"]["median"] / out["fp32"]["us"]["median"], 3)
     return out
 
 
-def copy_ceiling(steps: int = 50, sets: int = 4):
-    """A plain device copy of the headline kernel's bytes (128 MiB read and
-    128 MiB written per launch), as the achievable ceiling: torch's copy_ and
-    the HIP runtime's device-to-device memcpy, mean of HIP-event pairs."""
+def bench_lib():
+    """The benchmark's HBM streaming kernels (libsplitdft_bench.so)."""
+    import ctypes
+
+    from paper_2504_07264_amd import build
+
+    if not os.path.exists(build.BENCH_LIB_PATH):
+        raise RuntimeError("libsplitdft_bench.so is missing; build with `python -m paper_2504_07264_amd.build`")
+    L = ctypes.CDLL(build.BENCH_LIB_PATH)
+    L.splitdft_bench_stream.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
+                                        ctypes.c_void_p, ctypes.c_void_p]
+    L.splitdft_bench_stream.restype = ctypes.c_int
+    return L
+
+
+def copy_ceiling(iters: int = MIN_ITERS, sets: int = 4):
+    """The achievable HBM rate for the headline kernel's bytes (128 MiB read
+    and 128 MiB written per launch): 16-byte nontemporal streaming kernels
+    (copy, read-only, write-only), torch's copy_ and the HIP runtime's
+    device-to-device memcpy, each timed as the median of HIP-event intervals."""
     import ctypes
 
     import torch
@@ -266,40 +345,50 @@ def copy_ceiling(steps: int = 50, sets: int = 4):
     dev = torch.device("cuda", 0)
     src = [torch.randn(2 * N * BATCH, device=dev) for _ in range(sets)]
     dst = [torch.empty_like(src[0]) for _ in range(sets)]
-    nbytes = src[0].numel() * 4
+    sink = torch.zeros(1, device=dev)
+    nfl = src[0].numel()
+    nbytes = nfl * 4
     stream = torch.cuda.current_stream(dev)
+    s = stream.cuda_stream
     out = {"bytes_each_way": nbytes}
 
-    def timed(fn):
+    def timed(fn, moved):
         for k in range(5):
             fn(k)
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-        for k in range(steps):
-            ev[k][0].record(stream)
-            fn(k)
-            ev[k][1].record(stream)
-        torch.cuda.synchronize()
-        us = sum(a.elapsed_time(b) for a, b in ev) / steps * 1e3
-        return {"us": round(us, 2), "GBps": round(2 * nbytes / us / 1e3, 1)}
+        us = stats_us(event_times(fn, iters, stream))
+        return {"us": us, "GBps": round(moved / us["median"] / 1e3, 1)}
 
-    out["torch_copy"] = timed(lambda k: dst[k % sets].copy_(src[k % sets]))
+    L = bench_lib()
+
+    def probe(mode):
+        def fn(k):
+            rc = L.splitdft_bench_stream(src[k % sets].data_ptr(), dst[k % sets].data_ptr(), nfl, mode,
+                                         sink.data_ptr(), s)
+            if rc != 0:
+                raise RuntimeError("streaming kernel launch failed: hipError %d" % rc)
+        return fn
+
+    out["nt_float4_copy"] = timed(probe(0), 2 * nbytes)
+    out["nt_float4_read"] = timed(probe(1), nbytes)
+    out["nt_float4_write"] = timed(probe(2), nbytes)
+    out["torch_copy"] = timed(lambda k: dst[k % sets].copy_(src[k % sets]), 2 * nbytes)
     try:
         hip = ctypes.CDLL("libamdhip64.so", mode=ctypes.RTLD_GLOBAL)
         hip.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
                                        ctypes.c_void_p]
         hip.hipMemcpyAsync.restype = ctypes.c_int
         d2d = 3  # hipMemcpyDeviceToDevice
-        s = stream.cuda_stream
-        out["hip_memcpy_d2d"] = timed(lambda k: hip.hipMemcpyAsync(dst[k % sets].data_ptr(), src[k % sets].data_ptr(),
-                                                                   nbytes, d2d, s))
+        out["hip_memcpy_d2d"] = timed(lambda k: hip.hipMemcpyAsync(dst[k % sets].data_ptr(),
+                                                                   src[k % sets].data_ptr(), nbytes, d2d, s),
+                                      2 * nbytes)
     except OSError:
         out["hip_memcpy_d2d"] = None
     return out
 
 
-def dif_n1024(steps: int = 50, sets: int = 4):
+def dif_n1024(iters: int = MIN_ITERS, sets: int = 4):
     """Forward N=1024 x 16384 through the decimation-in-frequency schedule
-    (eq. 9), same inputs as the headline: mean launch time from HIP events."""
+    (eq. 9), same inputs as the headline: launch time statistics."""
     import torch
 
     from paper_2504_07264_amd import Plan, binding, inputs
@@ -313,20 +402,14 @@ def dif_n1024(steps: int = 50, sets: int = 4):
     with Plan(w.n, w.batch, binding.DIF) as plan:
         for k in range(5):
             plan.exec(*bufs[k % sets])
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-        for k in range(steps):
-            ev[k][0].record(stream)
-            plan.exec(*bufs[k % sets])
-            ev[k][1].record(stream)
-        torch.cuda.synchronize()
-        us = sum(a.elapsed_time(b) for a, b in ev) / steps * 1e3
-        return {"workload": "split_fft_n1024_b16384 forward, decimation in frequency (eq. 9)", "us": round(us, 2),
-                "GBps": round(16 * w.n * w.batch / us / 1e3, 1), "schedule": plan.describe()}
+        us = stats_us(event_times(lambda k: plan.exec(*bufs[k % sets]), iters, stream))
+        return {"workload": "split_fft_n1024_b16384 forward, decimation in frequency (eq. 9)", "us": us,
+                "GBps": round(16 * w.n * w.batch / us["median"] / 1e3, 1), "schedule": plan.describe()}
 
 
-def two_pass_large(reps: int = 20):
+def two_pass_large(iters: int = MIN_ITERS, sets: int = 4):
     """Forward N=2^15 x 512 and N=2^16 x 256 (2^24 points each, the two-pass
-    schedule): mean time per launch from events around back-to-back execs."""
+    schedule): launch time statistics over rotating buffer sets."""
     import torch
 
     from paper_2504_07264_amd import Plan, inputs
@@ -337,27 +420,22 @@ def two_pass_large(reps: int = 20):
     for m in (15, 16):
         n, batch = 1 << m, (1 << 24) >> m
         xr, xi = inputs.draw_planes(n, batch, "normal", 30 + m)
-        x = (xr.to(dev), xi.to(dev))
-        y = (torch.empty(batch, n, device=dev), torch.empty(batch, n, device=dev))
+        bufs = [(xr.to(dev), xi.to(dev), torch.empty(batch, n, device=dev), torch.empty(batch, n, device=dev))
+                for _ in range(sets)]
         with Plan(n, batch) as plan:
-            for _ in range(3):
-                plan.exec(x[0], x[1], y[0], y[1])
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(reps):
-                plan.exec(x[0], x[1], y[0], y[1])
-            e1.record(stream)
-            torch.cuda.synchronize()
-            us = e0.elapsed_time(e1) / reps * 1e3
-            res["n%d_b%d" % (n, batch)] = {"us": round(us, 2), "GBps": round(16 * n * batch / us / 1e3, 1),
+            for k in range(3):
+                plan.exec(*bufs[k % sets])
+            us = stats_us(event_times(lambda k: plan.exec(*bufs[k % sets]), iters, stream))
+            res["n%d_b%d" % (n, batch)] = {"us": us, "GBps": round(16 * n * batch / us["median"] / 1e3, 1),
                                           "schedule": plan.describe()}
-        del x, y
+        del bufs
     res["note"] = "forward only; GB/s counts 16 B per point, the two passes move twice that"
     return res
 
 
-def grad_n4096(steps: int = 30, sets: int = 3):
-    """Forward + adjoint (the autograd step's two kernels) at N=4096 x 4096."""
+def grad_n4096(iters: int = MIN_ITERS, sets: int = 3):
+    """Forward + adjoint (the autograd step's two kernels) at N=4096 x 4096,
+    as two launches and as one fused launch."""
     import torch
 
     from paper_2504_07264_amd import Plan, inputs
@@ -365,6 +443,7 @@ def grad_n4096(steps: int = 30, sets: int = 3):
     w = inputs.GRAD_N4096
     xr, xi, wr, wi = inputs.draw(w)
     dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
     bufs = [tuple(t.to(dev) for t in (xr, xi, wr, wi)) + tuple(torch.empty(w.batch, w.n, device=dev)
                                                              for _ in range(4)) for _ in range(sets)]
     with Plan(w.n, w.batch) as plan:
@@ -373,50 +452,57 @@ def grad_n4096(steps: int = 30, sets: int = 3):
             plan.exec(a, b, yr, yi)
             plan.adjoint(c, d, gr, gi)
 
+        def fused(k):
+            a, b, c, d, yr, yi, gr, gi = bufs[k % sets]
+            plan.exec_adjoint(a, b, c, d, out=(yr, yi, gr, gi))
+
         for k in range(3):
             step(k)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for k in range(steps):
-            step(k)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / steps
-        return {"workload": "split_fft_n4096_b4096 forward + adjoint", "ms_per_step": round(ms, 4),
-                "GBps": round(2 * 16 * w.n * w.batch / ms / 1e6, 1), "schedule": plan.describe()}
+            fused(k)
+        two = stats_us(event_times(step, iters, stream))
+        one = stats_us(event_times(fused, iters, stream))
+        nbytes = 2 * 16 * w.n * w.batch
+        return {"workload": "split_fft_n4096_b4096 forward + adjoint", "schedule": plan.describe(),
+                "two_launches_us": two, "two_launches_GBps": round(nbytes / two["median"] / 1e3, 1),
+                "fused_us": one, "fused_GBps": round(nbytes / one["median"] / 1e3, 1)}
 
 
-def ragged_grouped(reps: int = 10):
-    """20000 transforms of lengths 2^4..2^16, forward + adjoint, one
-    persistent launch replayed from a captured HIP graph."""
+def ragged_grouped(iters: int = MIN_ITERS // 2):
+    """20000 transforms of lengths 2^4..2^16, forward + adjoint, replayed from
+    a captured HIP graph: the default schedule and the autotuner's choice
+    (grouped-kernel build, workgroups per CU, per-length threshold), timed on
+    this device just before."""
     import torch
 
-    from paper_2504_07264_amd import ManyPlan, inputs
+    from paper_2504_07264_amd import ManyPlan, inputs, tune
 
     lengths, planes = inputs.draw_ragged(inputs.RAGGED_COUNT, inputs.RAGGED_KMIN, inputs.RAGGED_KMAX,
                                          inputs.RAGGED_SEED)
     dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
     total = int(lengths.sum())
     xr, xi, gr, gi = [t.to(dev) for t in planes]
     del planes
     out = [torch.empty(total, device=dev) for _ in range(4)]
-    with ManyPlan(lengths.numpy()) as plan:
-        g = plan.graph(xr, xi, out[0], out[1], gr, gi, out[2], out[3])
-        g.launch()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            g.launch()
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        info = plan.info()
-        g.close()
-    return {"workload": "20000 transforms, lengths 2^4..2^16 (k uniform, seed 4), forward + adjoint, one graph",
-            "points": total, "ms_per_launch": round(ms, 4), "GBps": round(32 * total / ms / 1e6, 1),
-            "workgroups": info["workgroups"], "items": info["items"]}
+    lens = [int(v) for v in lengths.tolist()]
+    t0 = time.perf_counter()
+    best, timings = tune.tune_many(lens, iters=5)
+    tune_s = time.perf_counter() - t0
+    res = {"workload": "20000 transforms, lengths 2^4..2^16 (k uniform, seed 4), forward + adjoint, one graph",
+           "points": total, "tune_s": round(tune_s, 2),
+           "tune_candidates_us": {str(k): v["us"] for k, v in timings.items()}}
+    for name, flags in (("default", 0), ("tuned", best)):
+        with ManyPlan(lens, flags) as plan:
+            g = plan.graph(xr, xi, out[0], out[1], gr, gi, out[2], out[3])
+            for _ in range(3):
+                g.launch()
+            us = stats_us(event_times(lambda k: g.launch(), iters, stream, group=1))
+            info = plan.info()
+            g.close()
+        res[name] = {"flags": int(flags), "ms_per_launch": round(us["median"] / 1e3, 4), "us": us,
+                     "GBps": round(32 * total / us["median"] / 1e3, 1), "workgroups": info["workgroups"],
+                     "items": info["items"]}
+    return res
 
 
 def main():
@@ -426,7 +512,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mfma", action="store_true", help="skip the matrix-core comparison")
-    ap.add_argument("--no-extra", action="store_true", help="skip the N=4096 and ragged side reports")
+    ap.add_argument("--no-extra", action="store_true", help="skip the side reports")
+    ap.add_argument("--no-tune", action="store_true", help="use the default schedule for the headline")
     ap.add_argument("--counters", nargs="?", const="n1024", default=None, choices=COUNTER_WORKLOADS,
                     help="only launch one workload's kernels and a calibration copy (for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -442,7 +529,7 @@ def main():
 
     import torch
 
-    from paper_2504_07264_amd import Plan, inputs
+    from paper_2504_07264_amd import Plan, inputs, tune
 
     assert torch.cuda.is_available(), "no GPU visible"
     dev = torch.device("cuda", 0)
@@ -450,6 +537,16 @@ def main():
     w = inputs.HEADLINE_N1024
     xr, xi = inputs.draw(w)
     gr, gi = inputs.draw_planes(N, BATCH, "normal", w.seed + 100)
+
+    # the autotuner's schedule for this length and batch, timed here
+    tuned = None
+    flags = 0
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        flags, timings = tune.tune_length(N, BATCH, iters=20)
+        tuned = {"flags": int(flags), "tune_s": round(time.perf_counter() - t0, 2),
+                 "candidates_us": {timings[f]["schedule"]: timings[f]["us"] for f in timings}}
+        torch.cuda.empty_cache()
 
     sets = []
     for k in range(ROTATE_SETS):
@@ -459,13 +556,25 @@ def main():
             "hr": torch.empty(BATCH, N, device=dev), "hi": torch.empty(BATCH, N, device=dev),
         }
         sets.append(s)
-    plan = Plan(N, BATCH)
+    plan = Plan(N, BATCH, flags)
     stream = torch.cuda.current_stream(dev)
 
     def step(k):
         s = sets[k % ROTATE_SETS]
         plan.exec(s["xr"], s["xi"], s["yr"], s["yi"])
         plan.adjoint(s["gr"], s["gi"], s["hr"], s["hi"])
+
+    def launch(k):
+        # launch k of the step sequence: forward for even k, adjoint for odd
+        s = sets[(k // 2) % ROTATE_SETS]
+        if k % 2 == 0:
+            plan.exec(s["xr"], s["xi"], s["yr"], s["yi"])
+        else:
+            plan.adjoint(s["gr"], s["gi"], s["hr"], s["hi"])
+
+    def fused_step(k):
+        s = sets[k % ROTATE_SETS]
+        plan.exec_adjoint(s["xr"], s["xi"], s["gr"], s["gi"], out=(s["yr"], s["yi"], s["hr"], s["hi"]))
 
     # Untimed: the GPU raises its clocks over the first few hundred
     # milliseconds of sustained work, so run steps for at least PREWARM_S
@@ -505,6 +614,11 @@ def main():
     achieved = launch_bytes / (launch_ms * 1e-3) / 1e9
     traffic = measured_traffic()
 
+    # a second timed region for the distribution: an event after every launch
+    per_launch = stats_us(event_times(launch, MIN_ITERS, stream, group=10))
+    two_launch_steps = stats_us(event_times(step, MIN_ITERS, stream, group=5))
+    fused_steps = stats_us(event_times(fused_step, MIN_ITERS, stream, group=5))
+
     out = {
         "metric": METRIC,
         "value": round(gbs, 2),
@@ -524,11 +638,15 @@ def main():
             "batch": BATCH,
             "inputs": "FP32 planar N(0,1), seeds 1 (x) and 101 (upstream gradient)",
             "schedule": plan.describe(),
+            "schedule_from": "autotuner" if tuned else "default",
             "rotating_buffer_sets": ROTATE_SETS,
         },
         "gflops_5nlogn": round(flops / (ms_per_step * 1e-3) / 1e9, 1),
         "kernel_us_per_launch": {"mean": round(launch_ms * 1e3, 2), "launches": launches,
-                                 "from": "HIP events at both ends of the timed region, launch stream"},
+                                 "from": "HIP events at both ends of the timed region, launch stream",
+                                 "distribution": per_launch,
+                                 "distribution_from": "a second region: %d groups of 10 back-to-back launches, "
+                                                      "one HIP event after each group" % MIN_ITERS},
         "roofline": {
             "bound": "hbm",
             "achieved": round(achieved, 1),
@@ -537,9 +655,14 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
         },
+        "step_us": {"two_launches": two_launch_steps, "fused_one_launch": fused_steps,
+                    "fused_GBps": round(step_bytes / fused_steps["median"] / 1e3, 1),
+                    "from": "%d groups of 5 back-to-back steps, one HIP event after each group" % MIN_ITERS},
+        "tuned": tuned,
         "device": device_info(dev),
     }
     del sets
+    plan.close()
     torch.cuda.empty_cache()
     if not args.no_mfma:
         out["mfma_vs_fp32"] = mfma_vs_fp32()
@@ -557,7 +680,6 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(xr, xi, gr, gi)
-    plan.close()
     print(json.dumps(out), flush=True)
 
 

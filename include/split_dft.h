@@ -317,7 +317,8 @@ split_dft_status split_dft_graph_launch(split_dft_graph_t graph, void *stream);
 split_dft_status split_dft_graph_destroy(split_dft_graph_t graph);
 split_dft_status split_dft_many_destroy(split_dft_many_t plan);
 
-const char *split_dft_status_string(split_dft_status status);
+/* Name of a status code; any other int gives "unknown status". */
+const char *split_dft_status_string(int status);
 const char *split_dft_last_error(void);
 
 #ifdef __cplusplus

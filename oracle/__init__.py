@@ -32,7 +32,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "split_oracle.c")
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB: another build of the same source (the host-sanitizer build of
+# the CPU tests); by default the in-tree one
+_LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 _lock = threading.Lock()
 
@@ -47,6 +49,15 @@ def build(force: bool = True) -> str:
         subprocess.check_call(["gcc", *_CFLAGS, _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
+
+
+def build_sanitized(path: str, cc: str = "clang") -> str:
+    """Compile split_oracle.c with AddressSanitizer + UndefinedBehaviorSanitizer
+    (clang, shared sanitizer runtime) into ``path``."""
+    flags = [f for f in _CFLAGS if f not in ("-O2", "-fopenmp")]
+    subprocess.check_call([cc, *flags, "-O1", "-g", "-fopenmp", "-fsanitize=address,undefined",
+                           "-fno-omit-frame-pointer", "-shared-libsan", _SRC, "-o", path, "-lm"])
+    return path
 
 
 def _load():

@@ -19,7 +19,9 @@ import threading
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libsplitdft.so")
+# SPLIT_DFT_LIB: another build of the same library (the host-sanitizer build
+# of the CPU tests); by default the in-tree one
+LIB_PATH = os.environ.get("SPLIT_DFT_LIB") or os.path.join(_PKG, "libsplitdft.so")
 
 OK = 0
 STATUS_NAMES = {

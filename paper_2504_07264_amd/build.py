@@ -17,6 +17,10 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD_DIR = os.path.join(PKG, "_build")
 LIB_PATH = os.path.join(PKG, "libsplitdft.so")
+# HBM streaming kernels for the benchmark's copy ceiling (not part of the
+# transform library)
+BENCH_LIB_PATH = os.path.join(PKG, "libsplitdft_bench.so")
+BENCH_SOURCES = ["bench_copy.hip"]
 
 SOURCES = ["fft_lds.hip", "fft_tile.hip", "fft_many.hip", "fft_mfma.hip", "twiddle.cpp", "mfma_tables.cpp",
            "api.cpp", "api_many.cpp", "noalloc.hip"]
@@ -44,34 +48,100 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found: the split-format DFT library needs ROCm's hipcc")
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source and link libsplitdft.so; returns its path."""
-    os.makedirs(BUILD_DIR, exist_ok=True)
-    cc = hipcc()
+def _compile(cc, src, verbose):
+    obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
+    lang = ["-x", "hip"] if src.endswith(".hip") else []
+    cmd = [cc, *HIPCC_FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("hipcc failed for %s:\n%s%s" % (src, res.stdout, res.stderr))
+    return obj
 
-    def compile_one(src):
-        obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-        lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [cc, *HIPCC_FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        res = subprocess.run(cmd, capture_output=True, text=True)
-        if res.returncode != 0:
-            raise RuntimeError("hipcc failed for %s:\n%s%s" % (src, res.stdout, res.stderr))
-        return obj
 
-    with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
-        objs = list(ex.map(compile_one, SOURCES))
-    tmp = LIB_PATH + ".tmp%d" % os.getpid()
+def _link(cc, objs, path, verbose):
+    tmp = path + ".tmp%d" % os.getpid()
     cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("link failed:\n%s%s" % (res.stdout, res.stderr))
-    os.replace(tmp, LIB_PATH)
+    os.replace(tmp, path)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every source and link libsplitdft.so (and the benchmark's
+    libsplitdft_bench.so); returns the transform library's path."""
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    cc = hipcc()
+    srcs = SOURCES + BENCH_SOURCES
+    with ThreadPoolExecutor(max_workers=min(4, len(srcs))) as ex:
+        objs = list(ex.map(lambda s: _compile(cc, s, verbose), srcs))
+    _link(cc, objs[:len(SOURCES)], LIB_PATH, verbose)
+    _link(cc, objs[len(SOURCES):], BENCH_LIB_PATH, verbose)
     return LIB_PATH
 
 
+# Host-side AddressSanitizer + UndefinedBehaviorSanitizer build, for CPU
+# tests: the host C++ sources (plan creation, argument validation, the C ABI,
+# table generation) are instrumented; the HIP sources (kernels and their
+# launchers) are linked from the regular build.
+SANITIZE_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-fno-omit-frame-pointer", "-shared-libsan", "-g", "-O1"]
+
+
+def asan_runtime() -> str:
+    """The clang AddressSanitizer runtime the sanitized builds link against
+    (to preload into an uninstrumented Python)."""
+    cc = hipcc()
+    res = subprocess.run([cc, "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = res.stdout.strip()
+    if res.returncode != 0 or not os.path.isabs(path) or not os.path.exists(path):
+        import glob
+
+        found = glob.glob("/opt/rocm/lib/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so")
+        if not found:
+            raise RuntimeError("clang AddressSanitizer runtime not found")
+        path = found[0]
+    return path
+
+
+def build_sanitized(out_dir: str, verbose: bool = False) -> str:
+    """Link out_dir/libsplitdft.so from ASan + UBSan builds of the host C++
+    sources and the regular objects of the HIP sources; returns its path."""
+    os.makedirs(out_dir, exist_ok=True)
+    cc = hipcc()
+    flags = [f for f in HIPCC_FLAGS if f != "-O3"] + SANITIZE_FLAGS
+
+    def one(src):
+        if src.endswith(".hip"):
+            obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
+            return obj if os.path.exists(obj) else _compile(cc, src, verbose)
+        obj = os.path.join(out_dir, os.path.splitext(src)[0] + ".o")
+        cmd = [cc, *flags, "-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError("sanitized compile failed for %s:\n%s%s" % (src, res.stdout, res.stderr))
+        return obj
+
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+        objs = list(ex.map(one, SOURCES))
+    path = os.path.join(out_dir, "libsplitdft.so")
+    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-Xarch_host", "-fsanitize=address", "-Xarch_host",
+           "-fsanitize=undefined", "-shared-libsan", *objs, "-o", path]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("sanitized link failed:\n%s%s" % (res.stdout, res.stderr))
+    return path
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    if "--sanitize" in sys.argv:
+        print(build_sanitized(sys.argv[sys.argv.index("--sanitize") + 1], verbose="-v" in sys.argv))
+    else:
+        print(build(verbose="-v" in sys.argv))

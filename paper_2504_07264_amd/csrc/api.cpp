@@ -564,7 +564,7 @@ split_dft_status split_dft_twiddle_table(int m, float* c, float* s)
     return SPLIT_DFT_OK;
 }
 
-const char* split_dft_status_string(split_dft_status status)
+const char* split_dft_status_string(int status)
 {
     switch (status) {
     case SPLIT_DFT_OK: return "ok";

@@ -62,18 +62,21 @@ def save_cache(data: dict, path=None) -> None:
     os.replace(tmp, path)
 
 
-def _time(fn, iters: int, warmup: int = 3) -> float:
-    """Median microseconds of fn(k) over ``iters`` launches (HIP events)."""
+def _time(fn, iters: int, warmup: int = 3, group: int = 4) -> float:
+    """Median microseconds per call of fn(k) over ``iters`` groups of
+    ``group`` back-to-back calls, one HIP event after each group (so that
+    consecutive kernels overlap as they do in use)."""
     for k in range(warmup):
         fn(k)
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(iters)]
-    for k in range(iters):
-        ev[k][0].record()
-        fn(k)
-        ev[k][1].record()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(iters + 1)]
+    ev[0].record()
+    for j in range(iters):
+        for k in range(j * group, (j + 1) * group):
+            fn(k)
+        ev[j + 1].record()
     torch.cuda.synchronize()
-    t = sorted(a.elapsed_time(b) for a, b in ev)
+    t = sorted(ev[j].elapsed_time(ev[j + 1]) / group for j in range(iters))
     return t[len(t) // 2] * 1e3
 
 
@@ -122,7 +125,7 @@ def tune_many(lengths, iters: int = 5):
         flags = many_flags(build, wpc, one_kernel, split)
         with ManyPlan(lengths, flags) as p:
             g = p.graph(*planes)
-            us = _time(lambda k: g.launch(), iters, warmup=1)
+            us = _time(lambda k: g.launch(), iters, warmup=1, group=1)
             g.close()
             timings[flags] = {"us": round(us, 1), "workgroups": p.info()["workgroups"], "one_kernel": one_kernel,
                               "per_length_from": split}

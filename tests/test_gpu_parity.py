@@ -14,6 +14,7 @@ import pytest
 import torch
 
 import oracle
+from guards import assert_guards_intact, guarded_empty
 from paper_2504_07264_amd import Plan, SplitDFTError, binding, inputs, variant_flag
 
 pytestmark = pytest.mark.gpu
@@ -173,7 +174,14 @@ def test_single_tone_sign(m):
 def test_headline_full_size():
     w = inputs.HEADLINE_N1024
     xr, xi = inputs.draw(w)
-    yr, yi = gpu_exec(w.n, w.batch, xr, xi)
+    say("  exec n=%d batch=%d into guarded outputs" % (w.n, w.batch))
+    with Plan(w.n, w.batch) as p:
+        (br, pr), (bi, pi) = guarded_empty(w.n * w.batch), guarded_empty(w.n * w.batch)
+        p.exec(xr.cuda(), xi.cuda(), pr.view(w.batch, w.n), pi.view(w.batch, w.n))
+        torch.cuda.synchronize()
+        assert_guards_intact(br, "yr")
+        assert_guards_intact(bi, "yi")
+        yr, yi = to_np(pr).reshape(w.batch, w.n), to_np(pi).reshape(w.batch, w.n)
     say("  oracle mirror + FP64 on %d rows" % w.batch)
     mr, mi = oracle.split_fft_f32(xr.numpy(), xi.numpy())
     assert_bit_exact(yr, yi, mr, mi)
@@ -188,7 +196,14 @@ def test_headline_full_size():
 def test_adjoint_full_size_n4096():
     w = inputs.GRAD_N4096
     xr, xi, wr, wi = inputs.draw(w)
-    yr, yi = gpu_exec(w.n, w.batch, wr, wi, adjoint=True)
+    say("  adjoint n=%d batch=%d into guarded outputs" % (w.n, w.batch))
+    with Plan(w.n, w.batch) as p:
+        (br, pr), (bi, pi) = guarded_empty(w.n * w.batch), guarded_empty(w.n * w.batch)
+        p.adjoint(wr.cuda(), wi.cuda(), pr.view(w.batch, w.n), pi.view(w.batch, w.n))
+        torch.cuda.synchronize()
+        assert_guards_intact(br, "gxr")
+        assert_guards_intact(bi, "gxi")
+        yr, yi = to_np(pr).reshape(w.batch, w.n), to_np(pi).reshape(w.batch, w.n)
     mr, mi = oracle.split_adjoint_f32(wr.numpy(), wi.numpy())
     assert_bit_exact(yr, yi, mr, mi)
     rows = np.random.default_rng(1).choice(w.batch, 16, replace=False)
