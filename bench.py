@@ -545,7 +545,9 @@ def main():
         t0 = time.perf_counter()
         flags, timings = tune.tune_length(N, BATCH, iters=20)
         tuned = {"flags": int(flags), "tune_s": round(time.perf_counter() - t0, 2),
-                 "candidates_us": {timings[f]["schedule"]: timings[f]["us"] for f in timings}}
+                 "candidates_us": {timings[f]["schedule"]: timings[f]["us"] for f in timings},
+                 "finalists_us": {timings[f]["schedule"]: timings[f]["final_us"] for f in timings
+                                  if "final_us" in timings[f]}}
         torch.cuda.empty_cache()
 
     sets = []

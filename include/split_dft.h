@@ -94,7 +94,8 @@ typedef enum {
  * (not bit-exact): */
 #define SPLIT_DFT_BF16X2 1u /* bf16 hi+lo, 3 products: rel. error ~4e-6         */
 #define SPLIT_DFT_FP16X2 2u /* fp16 hi+lo (lo scaled by 2^11), 3 products;
-                               needs |x| * 16 < 65504                            */
+                               each row scaled by a power of two into fp16's
+                               range (any finite input)                         */
 #define SPLIT_DFT_BF16X3 3u /* bf16 hi+mid+lo, 6 products                       */
 /* Bits 8-15: 0 = default kernel schedule, k = compiled FP32 schedule k-1
  * (used by tuning). */

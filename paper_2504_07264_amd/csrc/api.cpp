@@ -363,7 +363,9 @@ split_dft_status split_dft_plan(split_dft_plan_t* out, int64_t n, int64_t batch,
     float* d_mfma = nullptr;
     if (mode != splitdft::kModeFP32) {
         std::vector<float> tab(splitdft::kMfmaConstFloats + 2 * 256);
-        splitdft::build_mfma256_constants(mode, tab.data());
+        std::vector<uint16_t> enc(2 * splitdft::kMfmaConstFloats);
+        splitdft::build_mfma256_constants(mode, enc.data());
+        std::memcpy(tab.data(), enc.data(), sizeof(uint16_t) * enc.size());
         splitdft::build_tw256(tab.data() + splitdft::kMfmaConstFloats);
         e = hipMalloc(&d_mfma, sizeof(float) * tab.size());
         if (e == hipSuccess)

@@ -31,12 +31,15 @@
 //   BF16X2: lo*hi + hi*lo + hi*hi                     (3 MFMAs per product)
 //   BF16X3: lo2*hi + hi*lo2 + lo*lo + lo*hi + hi*lo + hi*hi  (6 MFMAs)
 //   FP16X2: lo parts scaled by 2^11 (kept normal), accumulated separately
-//           and scaled back: hi*hi + 2^-11 (lo*hi + hi*lo)   (3 MFMAs)
+//           and scaled back: hi*hi + 2^-11 (lo*hi + hi*lo)   (3 MFMAs);
+//           a row outside FP16's comfortable range is first scaled by a
+//           power of two (row_shift), so any finite input is accepted
 // The constant matrices are split on the host from FP64 values.
 #include "internal.h"
 
 #include <atomic>
 #include <climits>
+#include <type_traits>
 
 namespace splitdft {
 namespace {
@@ -128,20 +131,17 @@ __device__ __forceinline__ f32x4 product(const typename Prec<MODE>::V (&a)[Prec<
     }
 }
 
+// Operand `mat` (0..3) of this lane, every part: one 16-byte load each from
+// the table of 16-bit encodings.
 template <int MODE>
 __device__ __forceinline__ void load_const(const float* tab, int mat, int lane,
                                            typename Prec<MODE>::V (&p)[Prec<MODE>::PARTS])
 {
-    const float* src = tab + ((mat * 64 + lane) * 8) * 3;
+    using V = typename Prec<MODE>::V;
+    const V* src = reinterpret_cast<const V*>(tab);
 #pragma unroll
-    for (int r = 0; r < 8; ++r)
-#pragma unroll
-        for (int k = 0; k < Prec<MODE>::PARTS; ++k) {
-            if constexpr (MODE == kModeFP16X2)
-                p[k][r] = static_cast<_Float16>(src[r * 3 + k]);
-            else
-                p[k][r] = static_cast<__bf16>(src[r * 3 + k]);
-        }
+    for (int k = 0; k < Prec<MODE>::PARTS; ++k)
+        p[k] = src[(mat * 3 + k) * 64 + lane];
 }
 
 constexpr int kWaves = 4;
@@ -160,6 +160,50 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Maximum over the wave of a nonnegative value, wave-uniform: DPP row shifts
+// reduce each row of 16 lanes into its lane 15, two row broadcasts carry the
+// rows into lane 63, which is read back as a scalar.  Lanes a DPP move has no
+// source for read 0, the identity here.
+__device__ __forceinline__ float wave_max_nonneg(float v)
+{
+    auto step = [](float x, int ctrl, int row_mask, int bank_mask) {
+        const int y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, row_mask, bank_mask, false);
+        return __builtin_fmaxf(x, __int_as_float(y));
+    };
+    v = step(v, 0x111, 0xf, 0xf);  // row_shr:1
+    v = step(v, 0x112, 0xf, 0xf);  // row_shr:2
+    v = step(v, 0x114, 0xf, 0xe);  // row_shr:4
+    v = step(v, 0x118, 0xf, 0xc);  // row_shr:8
+    v = step(v, 0x142, 0xa, 0xf);  // row_bcast:15
+    v = step(v, 0x143, 0xc, 0xf);  // row_bcast:31
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+// FP16X2 range: the exponent k by which a row is scaled (x * 2^-k) before its
+// FP16 split, and its outputs scaled back (y * 2^k).  A 16-point DFT grows
+// magnitudes at most 32-fold (16 complex terms), so with the row's largest
+// magnitude m below 2^10 both contractions' operands stay below 2^15 < 65504;
+// and with m at least 2^-4 the row's significant values are normal FP16
+// numbers.  Rows with m in [2^-4, 2^10) are not scaled (k = 0); the others
+// are scaled to m * 2^-k in [2^9, 2^10), whatever their scale (k in
+// [-158, 118]; ldexp of the values themselves, so no scale factor has to be
+// representable).  Scaling by a power of two commutes with FP16 and FP32
+// rounding.  All-zero and non-finite rows are not scaled.  k is wave-uniform.
+__device__ __forceinline__ int row_shift(const v4f (&row)[2])
+{
+    float m = 0.0f;
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            m = __builtin_fmaxf(m, __builtin_fabsf(row[p][e]));
+    m = wave_max_nonneg(m);
+    if (!(m > 0.0f) || m == __builtin_inff() || (m >= 0.0625f && m < 1024.0f))
+        return 0;
+    // m = f * 2^e with f in [0.5, 1): m * 2^-k in [2^9, 2^10) for k = e - 10
+    return __builtin_amdgcn_frexp_expf(m) - 10;
+}
+
 // 16-byte loads of the TPI rows from b0 (zeros past the batch).
 template <int TPI>
 __device__ __forceinline__ void load_rows(v4f (&in)[TPI][2], const float* xr, const float* xi, int64_t b0,
@@ -173,6 +217,18 @@ __device__ __forceinline__ void load_rows(v4f (&in)[TPI][2], const float* xr, co
         } else {
             in[t][0] = in[t][1] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
         }
+    }
+}
+
+// The TPI rows from b0, all inside the batch.
+template <int TPI>
+__device__ __forceinline__ void load_rows_full(v4f (&in)[TPI][2], const float* xr, const float* xi, int64_t b0,
+                                               int lane)
+{
+#pragma unroll
+    for (int t = 0; t < TPI; ++t) {
+        in[t][0] = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(xr + (b0 + t) * 256) + lane);
+        in[t][1] = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(xi + (b0 + t) * 256) + lane);
     }
 }
 
@@ -207,18 +263,35 @@ split_fft256_mfma_kernel(const float* xr, const float* xi, float* yr, float* yi,
     const int a_off = (q >> 1) * kPlaneWords + pad256(128 * (q & 1) + c);
     // the grid is resident: each wave loops with a stride and issues the
     // next rows' loads before the current rows' arithmetic
+    const int64_t stride = nwaves * TPI;
+    // Rows go to LDS ("staged") one iteration ahead: an iteration issues the
+    // next rows' loads, computes the staged rows, stores their results, and
+    // then stages the next rows.  The loads are thus issued before the
+    // stores, and waiting for them (stores count in the same counter) does
+    // not wait for the stores.  FP16X2 also carries each staged row's scale
+    // exponent.
     v4f in[TPI][2];
-    if (wave * TPI < batch)
-        load_rows<TPI>(in, xr, xi, wave * TPI, batch, lane);
-    for (int64_t b0 = wave * TPI; b0 < batch; b0 += nwaves * TPI) {
+    int shift[TPI];
+    auto stage = [&]() {
 #pragma unroll
-        for (int t = 0; t < TPI; ++t)
+        for (int t = 0; t < TPI; ++t) {
 #pragma unroll
             for (int p = 0; p < 2; ++p)
                 *reinterpret_cast<v4f*>(my + (2 * t + p) * kPlaneWords + pad256(4 * lane)) = in[t][p];
+            shift[t] = MODE == kModeFP16X2 ? row_shift(in[t]) : 0;
+        }
         wave_lds_sync();
-        if (b0 + nwaves * TPI < batch)
-            load_rows<TPI>(in, xr, xi, b0 + nwaves * TPI, batch, lane);
+    };
+    // One iteration over the staged rows b0 .. b0 + TPI - 1.  FULL: these
+    // rows and the next iteration's are all in the batch, so every load and
+    // store is unconditional and the compiler counts them exactly.
+    auto iteration = [&](int64_t b0, auto full) {
+        constexpr bool FULL = decltype(full)::value;
+        const bool more = FULL || b0 + stride < batch;
+        if constexpr (FULL)
+            load_rows_full<TPI>(in, xr, xi, b0 + stride, lane);
+        else if (more)
+            load_rows<TPI>(in, xr, xi, b0 + stride, batch, lane);
 #pragma unroll
         for (int t = 0; t < TPI; ++t) {
             const float* src = my + 2 * t * kPlaneWords + a_off;
@@ -226,6 +299,10 @@ split_fft256_mfma_kernel(const float* xr, const float* xi, float* yr, float* yi,
 #pragma unroll
             for (int r = 0; r < 8; ++r)
                 v[r] = src[16 * r];
+            if (MODE == kModeFP16X2 && shift[t] != 0)  // wave-uniform
+#pragma unroll
+                for (int r = 0; r < 8; ++r)
+                    v[r] = __builtin_ldexpf(v[r], -shift[t]);
             V a[P::PARTS];
             split8<MODE>(v, a);
             const f32x4 xr4 = product<MODE>(a, b1r);
@@ -245,25 +322,44 @@ split_fft256_mfma_kernel(const float* xr, const float* xi, float* yr, float* yi,
             // transform's operand reads above are complete: the MFMAs used them)
             float* dr = my + 2 * t * kPlaneWords;
             float* di = dr + kPlaneWords;
+            f32x4 outr = yr4, outi = yi4;
+            if (MODE == kModeFP16X2 && shift[t] != 0)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    outr[r] = __builtin_ldexpf(yr4[r], shift[t]);
+                    outi[r] = __builtin_ldexpf(yi4[r], shift[t]);
+                }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                dr[pad256(c + 16 * (4 * q + r))] = yr4[r];
-                di[pad256(c + 16 * (4 * q + r))] = yi4[r];
+                dr[pad256(c + 16 * (4 * q + r))] = outr[r];
+                di[pad256(c + 16 * (4 * q + r))] = outi[r];
             }
         }
         wave_lds_sync();
 #pragma unroll
         for (int t = 0; t < TPI; ++t) {
-            if (b0 + t < batch) {
+            if (FULL || b0 + t < batch) {
                 const v4f o_r = *reinterpret_cast<const v4f*>(my + 2 * t * kPlaneWords + pad256(4 * lane));
                 const v4f o_i = *reinterpret_cast<const v4f*>(my + (2 * t + 1) * kPlaneWords + pad256(4 * lane));
                 __builtin_nontemporal_store(o_r, reinterpret_cast<v4f*>(yr + (b0 + t) * 256) + lane);
                 __builtin_nontemporal_store(o_i, reinterpret_cast<v4f*>(yi + (b0 + t) * 256) + lane);
             }
         }
-        // the next iteration's staging writes reuse this wave's LDS
+        // the staging writes below reuse this wave's LDS
         wave_lds_sync();
+        if (more)
+            stage();
+    };
+    int64_t b0 = wave * TPI;
+    if (b0 < batch) {
+        load_rows<TPI>(in, xr, xi, b0, batch, lane);
+        stage();
     }
+    for (; b0 + stride + TPI <= batch; b0 += stride)
+        iteration(b0, std::true_type{});
+    // at most two more iterations, partly outside the batch
+    for (; b0 < batch; b0 += stride)
+        iteration(b0, std::false_type{});
 }
 
 constexpr int kMaxDevices = 64;

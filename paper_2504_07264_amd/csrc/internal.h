@@ -137,12 +137,15 @@ constexpr int kModeBF16X2 = 1;
 constexpr int kModeFP16X2 = 2;
 constexpr int kModeBF16X3 = 3;
 
-// Words of the per-mode constant table of the length-256 matrix-core kernel.
-constexpr int kMfmaConstFloats = 4 * 64 * 8 * 3;
+// 32-bit words of the per-mode constant table of the length-256 matrix-core
+// kernel: 4 operands x 3 parts x 64 lanes x 8 16-bit values.
+constexpr int kMfmaConstFloats = 4 * 3 * 64 * 8 / 2;
 
 // Host: constant operands of the length-256 matrix-core kernel for `mode`,
-// split from FP64 into parts exactly representable in the low-precision type.
-void build_mfma256_constants(int mode, float* out);
+// split from FP64 into parts exactly representable in the low-precision type
+// and stored as that type's 16-bit encodings, 8 per lane and (operand, part):
+// entry ((mat * 3 + part) * 64 + lane) * 8 + r.
+void build_mfma256_constants(int mode, uint16_t* out);
 
 // Host: (cos, sin) of 2*pi*t/256 for t = 0..255 (exact at multiples of pi/4).
 void build_tw256(float* cs);

@@ -6,17 +6,22 @@
 // wave holds, for each of four constant operands, 8 entries (register r of
 // lane quarter q, column or row lane % 16).  The entries are formed in FP64
 // and split into hi (+ lo (+ lo2)) parts exactly representable in the
-// low-precision type; the FP16 lo part is scaled by 2^11.
+// low-precision type; the FP16 lo part is scaled by 2^11.  The parts are
+// stored in the type's encoding, so that each lane loads one (operand, part)
+// as one 16-byte vector.
 #include "internal.h"
 
 #include <cmath>
+#include <cstdint>
+#include <cstring>
 
 namespace splitdft {
 
 namespace {
 
 // Round to nearest (ties to even) with `bits` significand bits; the
-// constants here are far from the under/overflow limits of bf16 and fp16.
+// constants here are far from the under/overflow limits of bf16 and fp16
+// (every nonzero part is a normal number of its type).
 double round_bits(double v, int bits)
 {
     if (v == 0.0)
@@ -26,19 +31,35 @@ double round_bits(double v, int bits)
     return std::nearbyint(v * scale) / scale;
 }
 
-void split(double v, int mode, float* parts)
+// Encoding of v, exactly representable in the type: bf16 is the upper half
+// of the FP32 encoding; fp16 through the compiler's conversion.
+uint16_t encode(double v, int mode)
+{
+    if (mode == kModeFP16X2) {
+        const _Float16 h = static_cast<_Float16>(static_cast<float>(v));
+        uint16_t bits;
+        std::memcpy(&bits, &h, sizeof bits);
+        return bits;
+    }
+    const float f = static_cast<float>(v);
+    uint32_t bits;
+    std::memcpy(&bits, &f, sizeof bits);
+    return static_cast<uint16_t>(bits >> 16);
+}
+
+void split(double v, int mode, uint16_t* parts)
 {
     if (mode == kModeFP16X2) {
         const double h = round_bits(v, 11);
-        parts[0] = static_cast<float>(h);
-        parts[1] = static_cast<float>(round_bits((v - h) * 2048.0, 11));
-        parts[2] = 0.0f;
+        parts[0] = encode(h, mode);
+        parts[1] = encode(round_bits((v - h) * 2048.0, 11), mode);
+        parts[2] = 0;
     } else {
         const double h = round_bits(v, 8);
         const double l = round_bits(v - h, 8);
-        parts[0] = static_cast<float>(h);
-        parts[1] = static_cast<float>(l);
-        parts[2] = mode == kModeBF16X3 ? static_cast<float>(round_bits(v - h - l, 8)) : 0.0f;
+        parts[0] = encode(h, mode);
+        parts[1] = encode(l, mode);
+        parts[2] = mode == kModeBF16X3 ? encode(round_bits(v - h - l, 8), mode) : 0;
     }
 }
 
@@ -47,7 +68,7 @@ double sin16(int k) { double c, s; turn_fraction_f64(k & 15, 4, &c, &s); return 
 
 }  // namespace
 
-void build_mfma256_constants(int mode, float* out)
+void build_mfma256_constants(int mode, uint16_t* out)
 {
     for (int lane = 0; lane < 64; ++lane) {
         const int q = lane >> 4, c = lane & 15;
@@ -64,8 +85,12 @@ void build_mfma256_constants(int mode, float* out)
             const double a3r = re3 ? cos16(c * n0) : sin16(c * n0);
             const double a3i = re3 ? -sin16(c * n0) : cos16(c * n0);
             const double vals[4] = {b1r, b1i, a3r, a3i};
-            for (int mat = 0; mat < 4; ++mat)
-                split(vals[mat], mode, out + ((mat * 64 + lane) * 8 + r) * 3);
+            for (int mat = 0; mat < 4; ++mat) {
+                uint16_t parts[3];
+                split(vals[mat], mode, parts);
+                for (int k = 0; k < 3; ++k)
+                    out[((mat * 3 + k) * 64 + lane) * 8 + r] = parts[k];
+            }
         }
     }
 }

@@ -78,3 +78,20 @@ def test_mode_requires_n256():
         with pytest.raises(binding.SplitDFTError) as e:
             Plan(n, 4, binding.BF16X2)
         assert e.value.status_name == "UNSUPPORTED"
+
+
+@pytest.mark.parametrize("mode", ["fp16x2", "bf16x3", "bf16x2"])
+def test_any_input_scale(mode):
+    # rows scaled by powers of ten far outside FP16's range (and far below
+    # its normal range), plus an all-zero row: each row's error stays within
+    # the mode's bound (FP16X2 scales every row into range first)
+    xr, xi = inputs.draw_planes(256, 12, "uniform", 78)
+    scales = torch.tensor([1e-30, 1e-12, 1e-6, 1e-3, 1.0, 30.0, 1e3, 6e4, 1e6, 1e12, 1e30, 0.0])[:, None]
+    xr, xi = xr * scales, xi * scales
+    yr, yi = run(mode, xr, xi)
+    assert np.isfinite(yr).all() and np.isfinite(yi).all()
+    assert not yr[-1].any() and not yi[-1].any()
+    rr, ri = oracle.split_fft(xr.double().numpy()[:-1], xi.double().numpy()[:-1])
+    err = oracle.rel_l2_per_row(yr[:-1], yi[:-1], rr, ri)
+    say("  %s: per-scale rel L2 %s" % (mode, np.array2string(err, precision=2)))
+    assert err.max() <= TOL[mode]
