@@ -200,7 +200,7 @@ def cpu_baseline(xr, xi, gr, gi, budget_s: float = 2.0):
     }
 
 
-COUNTER_WORKLOADS = ("n1024", "two_pass", "n16384")
+COUNTER_WORKLOADS = ("n1024", "two_pass", "n16384", "n8192")
 
 
 def counters_run(workload: str = "n1024", reps: int = 5):
@@ -212,6 +212,7 @@ def counters_run(workload: str = "n1024", reps: int = 5):
     n1024     the forward length-1024 kernel, 16384 rows (the headline)
     two_pass  forward N=2^15 x 512 and N=2^16 x 256 (both passes each)
     n16384    forward N=2^14 x 1024 (single pass)
+    n8192     forward N=2^13 x 2048 (single pass)
     """
     import torch
 
@@ -226,6 +227,8 @@ def counters_run(workload: str = "n1024", reps: int = 5):
         shapes = [(1 << 15, 512), (1 << 16, 256)]
     elif workload == "n16384":
         shapes = [(1 << 14, 1024)]
+    elif workload == "n8192":
+        shapes = [(1 << 13, 2048)]
     else:
         raise SystemExit("unknown counters workload %r (one of %s)" % (workload, ", ".join(COUNTER_WORKLOADS)))
     report = []
@@ -430,6 +433,32 @@ def two_pass_large(iters: int = MIN_ITERS, sets: int = 4):
                                           "schedule": plan.describe()}
         del bufs
     res["note"] = "forward only; GB/s counts 16 B per point, the two passes move twice that"
+    return res
+
+
+def single_pass_large(iters: int = MIN_ITERS, sets: int = 4):
+    """Forward N=2^13 x 2048 and N=2^14 x 1024 (2^24 points each, the longest
+    single-pass lengths): launch time statistics over rotating buffer sets."""
+    import torch
+
+    from paper_2504_07264_amd import Plan, inputs
+
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    res = {}
+    for m in (13, 14):
+        n, batch = 1 << m, (1 << 24) >> m
+        xr, xi = inputs.draw_planes(n, batch, "normal", 30 + m)
+        bufs = [(xr.to(dev), xi.to(dev), torch.empty(batch, n, device=dev), torch.empty(batch, n, device=dev))
+                for _ in range(sets)]
+        with Plan(n, batch) as plan:
+            for k in range(3):
+                plan.exec(*bufs[k % sets])
+            us = stats_us(event_times(lambda k: plan.exec(*bufs[k % sets]), iters, stream))
+            res["n%d_b%d" % (n, batch)] = {"us": us, "GBps": round(16 * n * batch / us["median"] / 1e3, 1),
+                                          "frac_of_8TBps": round(16 * n * batch / us["median"] / 1e3 / HBM_PEAK_GBS, 4),
+                                          "schedule": plan.describe()}
+        del bufs
     return res
 
 
@@ -675,6 +704,8 @@ def main():
         out["dif_n1024"] = dif_n1024()
         torch.cuda.empty_cache()
         out["grad_n4096"] = grad_n4096()
+        torch.cuda.empty_cache()
+        out["single_pass_large"] = single_pass_large()
         torch.cuda.empty_cache()
         out["two_pass_large"] = two_pass_large()
         torch.cuda.empty_cache()
