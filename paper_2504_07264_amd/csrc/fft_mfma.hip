@@ -164,18 +164,21 @@ __device__ __forceinline__ void wave_lds_sync()
 // reduce each row of 16 lanes into its lane 15, two row broadcasts carry the
 // rows into lane 63, which is read back as a scalar.  Lanes a DPP move has no
 // source for read 0, the identity here.
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ float dpp_max_step(float x)
+{
+    const int y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, BANK_MASK, false);
+    return __builtin_fmaxf(x, __int_as_float(y));
+}
+
 __device__ __forceinline__ float wave_max_nonneg(float v)
 {
-    auto step = [](float x, int ctrl, int row_mask, int bank_mask) {
-        const int y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, row_mask, bank_mask, false);
-        return __builtin_fmaxf(x, __int_as_float(y));
-    };
-    v = step(v, 0x111, 0xf, 0xf);  // row_shr:1
-    v = step(v, 0x112, 0xf, 0xf);  // row_shr:2
-    v = step(v, 0x114, 0xf, 0xe);  // row_shr:4
-    v = step(v, 0x118, 0xf, 0xc);  // row_shr:8
-    v = step(v, 0x142, 0xa, 0xf);  // row_bcast:15
-    v = step(v, 0x143, 0xc, 0xf);  // row_bcast:31
+    v = dpp_max_step<0x111, 0xf, 0xf>(v);  // row_shr:1
+    v = dpp_max_step<0x112, 0xf, 0xf>(v);  // row_shr:2
+    v = dpp_max_step<0x114, 0xf, 0xe>(v);  // row_shr:4
+    v = dpp_max_step<0x118, 0xf, 0xc>(v);  // row_shr:8
+    v = dpp_max_step<0x142, 0xa, 0xf>(v);  // row_bcast:15
+    v = dpp_max_step<0x143, 0xc, 0xf>(v);  // row_bcast:31
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
@@ -197,6 +200,11 @@ __device__ __forceinline__ int row_shift(const v4f (&row)[2])
 #pragma unroll
         for (int e = 0; e < 4; ++e)
             m = __builtin_fmaxf(m, __builtin_fabsf(row[p][e]));
+    // the common case from two wave votes: the wave's maximum is in
+    // [2^-4, 2^10) exactly when no lane's is 2^10 or more and some lane's is
+    // 2^-4 or more (m is never NaN: fmax drops NaN operands)
+    if (__builtin_amdgcn_ballot_w64(m >= 1024.0f) == 0 && __builtin_amdgcn_ballot_w64(m >= 0.0625f) != 0)
+        return 0;
     m = wave_max_nonneg(m);
     if (!(m > 0.0f) || m == __builtin_inff() || (m >= 0.0625f && m < 1024.0f))
         return 0;
