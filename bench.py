@@ -200,7 +200,7 @@ def cpu_baseline(xr, xi, gr, gi, budget_s: float = 2.0):
     }
 
 
-COUNTER_WORKLOADS = ("n1024", "two_pass", "n16384", "n8192")
+COUNTER_WORKLOADS = ("n1024", "two_pass", "n16384", "n8192", "l2_handover")
 
 
 def counters_run(workload: str = "n1024", reps: int = 5):
@@ -213,7 +213,12 @@ def counters_run(workload: str = "n1024", reps: int = 5):
     two_pass  forward N=2^15 x 512 and N=2^16 x 256 (both passes each)
     n16384    forward N=2^14 x 1024 (single pass)
     n8192     forward N=2^13 x 2048 (single pass)
+    l2_handover  the L2 hand-over model (every configuration once, with the
+              copy kernel on the same bytes as its calibration)
     """
+    if workload == "l2_handover":
+        print(json.dumps({"counters_run": 1, "workload": workload, "result": l2_handover(reps=1)}), flush=True)
+        return
     import torch
 
     from paper_2504_07264_amd import Plan, inputs
@@ -333,7 +338,82 @@ def bench_lib():
     L.splitdft_bench_stream.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
                                         ctypes.c_void_p, ctypes.c_void_p]
     L.splitdft_bench_stream.restype = ctypes.c_int
+    L.splitdft_bench_l2_control_bytes.argtypes = []
+    L.splitdft_bench_l2_control_bytes.restype = ctypes.c_int64
+    L.splitdft_bench_l2_handover.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int] * 6 + [ctypes.c_void_p]
+    L.splitdft_bench_l2_handover.restype = ctypes.c_int
     return L
+
+
+# (tiles per transform, ring slots per XCD, self mode, workgroups)
+L2_CONFIGS = ((4, 4, 0, 512), (4, 8, 0, 512), (4, 12, 0, 512), (4, 8, 1, 512), (4, 2, 1, 512),
+              (8, 4, 0, 512), (8, 8, 0, 512), (8, 8, 1, 512))
+
+
+def l2_handover(reps: int = 3, per_xcd: int = 128):
+    """The L2 hand-over model of a two-pass transform (csrc/bench_l2.hip):
+    transforms of 4 tiles (256 KiB, the size of a 2^15 transform) and 8 tiles
+    (512 KiB, 2^16), 128 per XCD, every pass-2 tile gathering from every
+    pass-1 tile through a ring of slots per XCD, against a 16-byte copy of the
+    same bytes.  Each launch is timed alone (its control block is cleared
+    before it) and its output checked against the permuted input."""
+    import torch
+
+    L = bench_lib()
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    s = stream.cuda_stream
+    cb = L.splitdft_bench_l2_control_bytes()
+    ctl = torch.zeros((cb + 3) // 4, dtype=torch.int32, device=dev)
+    gen = torch.Generator(device=dev).manual_seed(11)
+    sink = torch.zeros(1, device=dev)
+    out = {"model": "pass-1 tiles of 64 KiB handed to pass-2 tiles through a per-XCD ring in L2; no arithmetic",
+           "transforms_per_xcd": per_xcd}
+
+    def event_us(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        rc = fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        if rc != 0:
+            raise RuntimeError("launch failed: hipError %d" % rc)
+        return a.elapsed_time(b) * 1e3
+
+    for tiles in sorted({c[0] for c in L2_CONFIGS}):
+        tf = tiles * 16384
+        n = 8 * per_xcd * tf
+        x = torch.randn(n, device=dev, generator=gen)
+        y = torch.empty_like(x)
+        moved = 2 * n * 4
+        copy = [event_us(lambda: L.splitdft_bench_stream(x.data_ptr(), y.data_ptr(), n, 0, sink.data_ptr(), s))
+                for _ in range(reps + 1)][1:]
+        rec = {"bytes_in": n * 4, "copy_us": round(sorted(copy)[len(copy) // 2], 1)}
+        rec["copy_GBps"] = round(moved / rec["copy_us"] / 1e3)
+        want = x.view(-1, tiles, tiles, 16384 // tiles).transpose(1, 2)
+        for (t, slots, self_mode, grid) in L2_CONFIGS:
+            if t != tiles:
+                continue
+            ring = torch.empty(8 * slots * tf, device=dev)
+            times, correct, timeouts = [], True, 0
+            for _ in range(reps):
+                ctl.zero_()
+                y.zero_()
+                times.append(event_us(lambda: L.splitdft_bench_l2_handover(
+                    x.data_ptr(), y.data_ptr(), ring.data_ptr(), ctl.data_ptr(), grid, per_xcd, tiles, slots,
+                    self_mode, 1 << 16, s)))
+                tail = ctl[-3:].tolist()
+                timeouts += tail[0] + tail[1]
+                correct &= bool(torch.equal(y, x) if self_mode else torch.equal(y.view_as(want), want))
+            us = sorted(times)[len(times) // 2]
+            rec["slots%d%s" % (slots, "_self" if self_mode else "")] = {
+                "ring_MiB_per_xcd": slots * tf * 4 / 2**20, "workgroups": grid, "us": round(us, 1),
+                "GBps_in_out": round(moved / us / 1e3), "vs_copy": round(us / rec["copy_us"], 2),
+                "correct": correct, "timeouts": timeouts}
+            del ring
+        out["tiles%d" % tiles] = rec
+        del x, y
+    return out
 
 
 def copy_ceiling(iters: int = MIN_ITERS, sets: int = 4):
@@ -543,6 +623,8 @@ def main():
     ap.add_argument("--no-mfma", action="store_true", help="skip the matrix-core comparison")
     ap.add_argument("--no-extra", action="store_true", help="skip the side reports")
     ap.add_argument("--no-tune", action="store_true", help="use the default schedule for the headline")
+    ap.add_argument("--l2-handover", action="store_true",
+                    help="only the L2 hand-over model of a two-pass transform (one JSON line)")
     ap.add_argument("--counters", nargs="?", const="n1024", default=None, choices=COUNTER_WORKLOADS,
                     help="only launch one workload's kernels and a calibration copy (for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -554,6 +636,9 @@ def main():
 
     if args.counters:
         counters_run(args.counters)
+        return
+    if args.l2_handover:
+        print(json.dumps({"l2_handover": l2_handover()}), flush=True)
         return
 
     import torch

@@ -17,10 +17,10 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD_DIR = os.path.join(PKG, "_build")
 LIB_PATH = os.path.join(PKG, "libsplitdft.so")
-# HBM streaming kernels for the benchmark's copy ceiling (not part of the
-# transform library)
+# Benchmark-only kernels, not part of the transform library: HBM streaming
+# for the copy ceiling, and the L2 hand-over model of a two-pass transform
 BENCH_LIB_PATH = os.path.join(PKG, "libsplitdft_bench.so")
-BENCH_SOURCES = ["bench_copy.hip"]
+BENCH_SOURCES = ["bench_copy.hip", "bench_l2.hip"]
 
 SOURCES = ["fft_lds.hip", "fft_tile.hip", "fft_many.hip", "fft_mfma.hip", "twiddle.cpp", "mfma_tables.cpp",
            "api.cpp", "api_many.cpp", "noalloc.hip"]
