@@ -200,7 +200,7 @@ def cpu_baseline(xr, xi, gr, gi, budget_s: float = 2.0):
     }
 
 
-COUNTER_WORKLOADS = ("n1024", "two_pass", "n16384", "n8192", "l2_handover")
+COUNTER_WORKLOADS = ("n1024", "two_pass", "two_pass_fused", "n16384", "n8192", "l2_handover")
 
 
 def counters_run(workload: str = "n1024", reps: int = 5):
@@ -211,6 +211,8 @@ def counters_run(workload: str = "n1024", reps: int = 5):
 
     n1024     the forward length-1024 kernel, 16384 rows (the headline)
     two_pass  forward N=2^15 x 512 and N=2^16 x 256 (both passes each)
+    two_pass_fused  the same through the fused two-pass schedule (one launch
+              each, intermediate handed over through a per-XCD ring)
     n16384    forward N=2^14 x 1024 (single pass)
     n8192     forward N=2^13 x 2048 (single pass)
     l2_handover  the L2 hand-over model (every configuration once, with the
@@ -228,7 +230,7 @@ def counters_run(workload: str = "n1024", reps: int = 5):
     dst = torch.empty_like(src)
     if workload == "n1024":
         shapes = [(N, BATCH)]
-    elif workload == "two_pass":
+    elif workload in ("two_pass", "two_pass_fused"):
         shapes = [(1 << 15, 512), (1 << 16, 256)]
     elif workload == "n16384":
         shapes = [(1 << 14, 1024)]
@@ -244,7 +246,8 @@ def counters_run(workload: str = "n1024", reps: int = 5):
             xr, xi = inputs.draw_planes(n, batch, "normal", 30 + int(math.log2(n)))
         xr, xi = xr.to(dev), xi.to(dev)
         yr, yi = torch.empty_like(xr), torch.empty_like(xi)
-        with Plan(n, batch) as plan:
+        flags = fused_schedule_flags(int(math.log2(n))) if workload == "two_pass_fused" else 0
+        with Plan(n, batch, flags, own_workspace=True) as plan:
             for _ in range(reps):
                 plan.exec(xr, xi, yr, yi)
                 torch.cuda.synchronize()
@@ -490,9 +493,25 @@ def dif_n1024(iters: int = MIN_ITERS, sets: int = 4):
                 "GBps": round(16 * w.n * w.batch / us["median"] / 1e3, 1), "schedule": plan.describe()}
 
 
+def fused_schedule_flags(m: int):
+    """Plan flags of the compiled fused two-pass schedule of length 2^m, or None."""
+    from paper_2504_07264_amd import Plan, SplitDFTError, variant_flag
+
+    k = 0
+    while True:
+        try:
+            with Plan(1 << m, 1, variant_flag(k)) as p:
+                if "fused" in p.describe():
+                    return variant_flag(k)
+        except SplitDFTError:
+            return None
+        k += 1
+
+
 def two_pass_large(iters: int = MIN_ITERS, sets: int = 4):
-    """Forward N=2^15 x 512 and N=2^16 x 256 (2^24 points each, the two-pass
-    schedule): launch time statistics over rotating buffer sets."""
+    """Forward N=2^15 x 512 and N=2^16 x 256 (2^24 points each): launch time
+    statistics over rotating buffer sets, for the default schedule and the
+    fused two-pass schedule (both passes in one launch through a per-XCD ring)."""
     import torch
 
     from paper_2504_07264_amd import Plan, inputs
@@ -505,12 +524,18 @@ def two_pass_large(iters: int = MIN_ITERS, sets: int = 4):
         xr, xi = inputs.draw_planes(n, batch, "normal", 30 + m)
         bufs = [(xr.to(dev), xi.to(dev), torch.empty(batch, n, device=dev), torch.empty(batch, n, device=dev))
                 for _ in range(sets)]
-        with Plan(n, batch) as plan:
-            for k in range(3):
-                plan.exec(*bufs[k % sets])
-            us = stats_us(event_times(lambda k: plan.exec(*bufs[k % sets]), iters, stream))
-            res["n%d_b%d" % (n, batch)] = {"us": us, "GBps": round(16 * n * batch / us["median"] / 1e3, 1),
-                                          "schedule": plan.describe()}
+        for name, flags in (("default", 0), ("fused", fused_schedule_flags(m))):
+            if flags is None:
+                continue
+            with Plan(n, batch, flags, own_workspace=True) as plan:
+                for k in range(3):
+                    plan.exec(*bufs[k % sets])
+                us = stats_us(event_times(lambda k: plan.exec(*bufs[k % sets]), iters, stream))
+                rec = {"us": us, "GBps": round(16 * n * batch / us["median"] / 1e3, 1), "schedule": plan.describe()}
+            if name == "default":
+                res["n%d_b%d" % (n, batch)] = rec
+            else:
+                res["n%d_b%d" % (n, batch)]["fused"] = rec
         del bufs
     res["note"] = "forward only; GB/s counts 16 B per point, the two passes move twice that"
     return res

@@ -175,6 +175,16 @@ split_dft_status check_device(const split_dft_plan_s* p)
 split_dft_status launch_dirs(const split_dft_plan_s* p, const Io* dir, int ndir, float* w, int64_t chunk,
                              hipStream_t st)
 {
+    if (p->two && p->two->fused) {
+        // both passes in one launch per direction, the ring and its control block in w
+        for (int k = 0; k < ndir; ++k) {
+            const hipError_t e =
+                p->two->fused(dir[k].xr, dir[k].xi, dir[k].yr, dir[k].yi, p->d_tw, p->batch, nullptr, w, st);
+            if (e != hipSuccess)
+                return fail_hip(e, "fused two-pass kernel launch");
+        }
+        return SPLIT_DFT_OK;
+    }
     if (p->two) {
         float* wr = w;
         float* wi = w + chunk * p->n;
@@ -269,6 +279,14 @@ split_dft_status exec_in_scratch(split_dft_plan_t p, const float* xr, const floa
         const hipError_t e = lookup(p->device, &w, &cap);
         if (e != hipSuccess)
             return fail_hip(e, "address of the static scratch array");
+        if (p->two->fused) {
+            if (cap < splitdft::fused_workspace_bytes(p->two))
+                return fail(SPLIT_DFT_ERR_UNSUPPORTED, "the fused schedule's ring (" +
+                                                           std::to_string(splitdft::fused_workspace_bytes(p->two)) +
+                                                           " bytes) exceeds the static scratch (" +
+                                                           std::to_string(cap) + " bytes)");
+            return launch_dirs(p, io, 1, w, chunk, static_cast<hipStream_t>(stream));
+        }
         const int64_t per = p->n * 2 * static_cast<int64_t>(sizeof(float));
         const int64_t fit = static_cast<int64_t>(cap) / per;
         if (fit < 1)
@@ -392,6 +410,11 @@ split_dft_status split_dft_plan(split_dft_plan_t* out, int64_t n, int64_t batch,
         const int64_t nchunks = (batch + chunk - 1) / chunk;
         chunk = (batch + nchunks - 1) / nchunks;
         ws_bytes = static_cast<size_t>(chunk) * static_cast<size_t>(n) * 2 * sizeof(float);
+        if (two->fused) {
+            // one launch over the whole batch through the ring
+            chunk = batch;
+            ws_bytes = splitdft::fused_workspace_bytes(two);
+        }
         e = caller_ws ? hipSuccess : hipMalloc(&d_ws, ws_bytes);
         if (e != hipSuccess) {
             if (d_mfma)
@@ -541,6 +564,13 @@ split_dft_status split_dft_plan_describe(split_dft_plan_t plan, char* buf, size_
     }
     if (plan->two) {
         const splitdft::TwoPass* t = plan->two;
+        if (t->fused) {
+            std::snprintf(buf, len,
+                          "two-pass fused a=%d: %d blocks / %d columns per tile, %d threads, lds=%d, "
+                          "ring %d transforms per XCD",
+                          t->a, t->c1, t->c2, t->threads1, t->lds1 > t->lds2 ? t->lds1 : t->lds2, t->slots);
+            return SPLIT_DFT_OK;
+        }
         std::snprintf(buf, len,
                       "two-pass a=%d: pass1 %d blocks/wg %d threads lds=%d, pass2 %d columns/wg %d threads lds=%d "
                       "gf=%d ws=%s, chunk=%lld",

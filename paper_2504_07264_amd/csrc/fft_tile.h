@@ -4,6 +4,8 @@
 
 #include "fft_device.h"
 
+#include <type_traits>
+
 namespace splitdft {
 namespace {
 
@@ -99,18 +101,50 @@ __device__ __forceinline__ int tile_src_offset(int r, int i, const CS& tc)
         return tile_col<TC, CS>(tc, i) + (r << TC::A);  // workspace row r
 }
 
+// Sources of a tile's plane: a pointer read with 16-byte loads (nontemporal
+// for the data side of pass 1) ...
+template <bool NT>
+struct PlaneSrc {
+    const float* p;
+    __device__ __forceinline__ v4f load(int off) const { return load4<NT>(p + off); }
+};
+
+// ... or a plane another workgroup of the same XCD has just written, read
+// through a buffer resource with loads that bypass the CU's own cache and read
+// the XCD's L2 (cache policy sc1), so that no line the CU cached before the
+// other workgroup's stores can be returned.
+struct L2Src {
+    __amdgpu_buffer_rsrc_t rsrc;
+    __device__ __forceinline__ v4f load(int off) const
+    {
+        return __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(rsrc, static_cast<unsigned>(off) * 4u,
+                                                                             0, 16));
+    }
+};
+
+// Buffer resource over `floats` floats from p (raw 32-bit format, offsets in
+// bytes; accesses beyond the range read 0 instead of faulting).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(float* p, int floats)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(p, static_cast<short>(0), floats * 4, 0x00020000);
+}
+
+struct NoHook {
+    __device__ __forceinline__ void operator()() const {}
+};
+
 // tile_in in two steps, so that both planes' loads can be in flight at once:
 // this thread's 16-byte vectors of one plane of the tile ...
 // Vector c of a thread covers tile row tid / C4 + c * THREADS / C4 and tile
 // columns 4 * (tid % C4) .. + 3 (THREADS is a multiple of C4 = C / 4).
-template <class TC, class CS>
-__device__ __forceinline__ void tile_load(v4f (&r)[TC::E / 4], const float* src, const CS& tc, int tid)
+template <class TC, class CS, class Src>
+__device__ __forceinline__ void tile_load(v4f (&r)[TC::E / 4], const Src& src, const CS& tc, int tid)
 {
     constexpr int C4 = TC::C / 4, RSTEP = TC::THREADS / C4;
     const int c4 = tid % C4, r0 = tid / C4;
 #pragma unroll
     for (int c = 0; c < TC::E / 4; ++c)
-        r[c] = load4<TC::PASS == 1>(src + tile_src_offset<TC, CS>(r0 + c * RSTEP, 4 * c4, tc));
+        r[c] = src.load(tile_src_offset<TC, CS>(r0 + c * RSTEP, 4 * c4, tc));
 }
 
 // ... and into the LDS slots (layout of tile_in).
@@ -220,11 +254,14 @@ __device__ __forceinline__ void regs_tile(const float (&v)[TC::E], float* slot, 
 }
 
 // One tile of a pass: the C groups (columns) tile_col(tc, 0 .. C - 1) of the
-// transform whose planes start at xr, xi (source) and yr, yi (destination).
-// lds holds LDS_WORDS floats; every thread of the workgroup takes part.
-template <class TC, class CS>
-__device__ __forceinline__ void tile_process(const float* xr, const float* xi, float* yr, float* yi,
-                                             const float2* __restrict__ tw, const CS& tc, float* lds, int tid)
+// transform whose source planes are sr, si and whose destination planes start
+// at yr, yi.  lds holds LDS_WORDS floats; every thread of the workgroup takes
+// part.  after_loads() runs once every thread's loads of the tile have been
+// consumed (behind a workgroup barrier; split-plane tiles only).
+template <class TC, class CS, class Src, class Hook>
+__device__ __forceinline__ void tile_process(const Src& sr, const Src& si, float* yr, float* yi,
+                                             const float2* __restrict__ tw, const CS& tc, float* lds, int tid,
+                                             const Hook& after_loads)
 {
     constexpr int E = TC::E, LT = TC::LT, T = TC::T, C = TC::C;
     const int g = TC::GF ? tid % C : tid >> LT;  // group (column) within the tile
@@ -237,18 +274,20 @@ __device__ __forceinline__ void tile_process(const float* xr, const float* xi, f
     if constexpr (TC::SPLIT) {
         // both planes' loads in flight at once; LDS holds one plane at a time
         v4f pr[E / 4], pi[E / 4];
-        tile_load<TC, CS>(pr, xr, tc, tid);
-        tile_load<TC, CS>(pi, xi, tc, tid);
+        tile_load<TC, CS>(pr, sr, tc, tid);
+        tile_load<TC, CS>(pi, si, tc, tid);
         tile_put<TC>(pr, lds, tid);
         __syncthreads();
         tile_regs<TC>(vr, lr, t);
         __syncthreads();
         tile_put<TC>(pi, lds, tid);
         __syncthreads();
+        after_loads();
         tile_regs<TC>(vi, lr, t);
     } else {
-        tile_in<TC, CS>(xr, lds, tc, tid);
-        tile_in<TC, CS>(xi, area_i, tc, tid);
+        static_assert(std::is_same<Hook, NoHook>::value, "load hooks need split-plane tiles");
+        tile_in<TC, CS>(sr.p, lds, tc, tid);
+        tile_in<TC, CS>(si.p, area_i, tc, tid);
         __syncthreads();
         tile_regs<TC>(vr, lr, t);
         tile_regs<TC>(vi, li, t);
@@ -291,6 +330,14 @@ __device__ __forceinline__ void tile_process(const float* xr, const float* xi, f
     }
 }
 
+// The same from plane pointers (nontemporal loads on pass 1's data side).
+template <class TC, class CS>
+__device__ __forceinline__ void tile_process(const float* xr, const float* xi, float* yr, float* yi,
+                                             const float2* __restrict__ tw, const CS& tc, float* lds, int tid)
+{
+    tile_process<TC, CS>(PlaneSrc<TC::PASS == 1>{xr}, PlaneSrc<TC::PASS == 1>{xi}, yr, yi, tw, tc, lds, tid,
+                         NoHook{});
+}
 
 }  // namespace
 }  // namespace splitdft

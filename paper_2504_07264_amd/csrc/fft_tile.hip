@@ -27,7 +27,9 @@
 // is exactly that of eq. (6) in order, so results equal the single-pass
 // kernels' bit for bit.
 #include "fft_tile.h"
+#include "fft_xcd.h"
 
+#include <atomic>
 #include <climits>
 #include <cstdint>
 
@@ -81,33 +83,104 @@ hipError_t launch_tile(const float* xr, const float* xi, float* yr, float* yi, c
     return hipGetLastError();
 }
 
+// Polls per wait of the fused schedule before it gives up (each poll sleeps
+// up to about 0.4 us after a load from L2: seconds in all).
+constexpr int kXcdPollLimit = 1 << 22;
+
+// Launch of the fused schedule: the control block (after the ring in ws)
+// cleared by a kernel (graph-safe), then one persistent launch sized to the
+// device's resident capacity.
+template <class P1, class P2, int SLOTS>
+hipError_t launch_xcd(const float* xr, const float* xi, float* yr, float* yi, const float2* tw, int64_t batch,
+                      const int64_t* rows, float* ws, hipStream_t stream)
+{
+    static_assert(SLOTS >= 1 && SLOTS <= kXcdMaxSlots, "ring slots");
+    if (batch < 1 || batch >= kClaimedEmpty)
+        return hipErrorInvalidValue;
+    float* ring = ws;
+    auto* ctl = reinterpret_cast<XcdControl*>(ws + xcd_ring_floats(P1::M, SLOTS));
+    const bool rot = rows != nullptr || line_offset(xr) != 0;
+    auto kernel = rot ? split_fft_xcd_kernel<P1, P2, true> : split_fft_xcd_kernel<P1, P2, false>;
+    static std::atomic<int> resident_of[2][64];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    const bool cache = dev >= 0 && dev < 64;
+    int resident = cache ? resident_of[rot][dev].load(std::memory_order_relaxed) : 0;
+    if (resident <= 0) {
+        int cus = 0, per_cu = 0;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, P1::THREADS, 0);
+        if (e != hipSuccess)
+            return e;
+        if (per_cu < 1 || cus < 1)
+            return hipErrorInvalidConfiguration;
+        resident = cus * per_cu;
+        if (cache)
+            resident_of[rot][dev].store(resident, std::memory_order_relaxed);
+    }
+    // As many workgroups as are resident at once, fewer for small batches
+    // (more than the items would only take empty ones) but never fewer than
+    // T per XCD: the T tiles of a transform wait on each other, and workgroups
+    // are dispatched to the XCDs in turn.
+    const int64_t items = batch * P1::TILES;
+    const int64_t least = int64_t{kXcds} * P1::TILES;
+    int64_t grid = items > least ? items : least;
+    if (grid > resident)
+        grid = resident;
+    if (resident < least)
+        return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(xcd_control_clear, dim3(1), dim3(256), 0, stream, reinterpret_cast<int*>(ctl),
+                       static_cast<int>(sizeof(XcdControl) / sizeof(int)));
+    hipLaunchKernelGGL(kernel, dim3(static_cast<unsigned>(grid)), dim3(P1::THREADS), 0, stream, xr, xi, yr, yi, tw,
+                       batch, rows, ring, ctl, SLOTS, kXcdPollLimit);
+    return hipGetLastError();
+}
+
 template <int M, int A, int RB1, int C1, bool SPLIT1, int RB2, int C2, bool SPLIT2, bool GF2 = false,
-          bool WST = false>
+          bool WST = false, int SLOTS = 0>
 constexpr TwoPass make_two_pass()
 {
     constexpr int WSC = WST ? C2 : 0;
     using P1 = TileCfg<M, A, 1, RB1, C1, SPLIT1, false, WSC>;
     using P2 = TileCfg<M, A, 2, RB2, C2, SPLIT2, GF2, WSC>;
-    return TwoPass{M,  A,  C1, C2, P1::THREADS, P2::THREADS, 4 * P1::LDS_WORDS, 4 * P2::LDS_WORDS, GF2,
-                   &launch_tile<P1>, &launch_tile<P2>, WST};
+    if constexpr (SLOTS > 0)
+        return TwoPass{M,  A,  C1, C2, P1::THREADS, P2::THREADS, 4 * P1::LDS_WORDS, 4 * P2::LDS_WORDS, GF2,
+                       &launch_tile<P1>, &launch_tile<P2>, WST, &launch_xcd<P1, P2, SLOTS>, SLOTS};
+    else
+        return TwoPass{M,  A,  C1, C2, P1::THREADS, P2::THREADS, 4 * P1::LDS_WORDS, 4 * P2::LDS_WORDS, GF2,
+                       &launch_tile<P1>, &launch_tile<P2>, WST};
 }
 
 //                                   M   A  RB1 C1 SPLIT1 RB2 C2 SPLIT2 GF2
 const TwoPass kTwoPass14[] = {make_two_pass<14, 8, 4, 32, true, 4, 128, true, true, true>(),
                               make_two_pass<14, 8, 4, 32, true, 4, 64, true, true, true>(),
                               make_two_pass<14, 8, 4, 32, true, 4, 32, true, true>()};
+// the last entries of the 2^15 and 2^16 lists: both passes in one launch
+// through a ring of 12 (2^15, 3 MiB) or 8 (2^16, 4 MiB) transforms per XCD, the
+// fastest ring sizes measured (112 / 110 us per 2^24 points against 90 / 92
+// for the separate passes, so not the default)
 const TwoPass kTwoPass15[] = {make_two_pass<15, 8, 4, 32, true, 4, 64, true, true, true>(),
                               make_two_pass<15, 8, 4, 64, true, 4, 64, true, true, true>(),
                               make_two_pass<15, 8, 4, 32, true, 4, 128, true, true, true>(),
                               make_two_pass<15, 8, 4, 32, true, 4, 32, true, true>(),
-                              make_two_pass<15, 8, 4, 16, false, 4, 32, false>()};
+                              make_two_pass<15, 8, 4, 16, false, 4, 32, false>(),
+                              make_two_pass<15, 8, 4, 32, true, 4, 64, true, true, true, 12>()};
 const TwoPass kTwoPass16[] = {make_two_pass<16, 8, 4, 32, true, 4, 32, true, true, true>(),
                               make_two_pass<16, 8, 4, 64, true, 4, 32, true, true, true>(),
                               make_two_pass<16, 8, 4, 32, true, 4, 64, true, true, true>(),
                               make_two_pass<16, 8, 4, 32, true, 4, 32, true, true>(),
-                              make_two_pass<16, 8, 4, 16, false, 4, 16, false>()};
+                              make_two_pass<16, 8, 4, 16, false, 4, 16, false>(),
+                              make_two_pass<16, 8, 4, 32, true, 4, 32, true, true, true, 8>()};
 
 }  // namespace
+
+size_t fused_workspace_bytes(const TwoPass* t)
+{
+    return static_cast<size_t>(xcd_ring_floats(t->m, t->slots)) * sizeof(float) + xcd_control_bytes();
+}
 
 const TwoPass* two_pass_for(int m, int* count)
 {

@@ -61,7 +61,15 @@ struct TwoPass {
     hipError_t (*pass2)(const float* wr, const float* wi, float* yr, float* yi, const float2* tw, int64_t batch,
                         const int64_t* rows, hipStream_t stream);
     bool wst;  // workspace in pass-2 tile order (else natural position order)
+    // both passes in one launch, the intermediate handed over through a ring of
+    // `slots` transforms per XCD in the workspace (NULL: separate passes)
+    hipError_t (*fused)(const float* xr, const float* xi, float* yr, float* yi, const float2* tw, int64_t batch,
+                        const int64_t* rows, float* ws, hipStream_t stream) = nullptr;
+    int slots = 0;
 };
+
+// Workspace bytes of a fused two-pass schedule (ring and control block).
+size_t fused_workspace_bytes(const TwoPass* t);
 
 // Offset in floats, modulo 32, of a plane pointer from a 128-byte line.
 inline int line_offset(const float* p) { return static_cast<int>((reinterpret_cast<uintptr_t>(p) >> 2) & 31); }
