@@ -422,8 +422,10 @@ def l2_handover(reps: int = 3, per_xcd: int = 128):
 def copy_ceiling(iters: int = MIN_ITERS, sets: int = 4):
     """The achievable HBM rate for the headline kernel's bytes (128 MiB read
     and 128 MiB written per launch): 16-byte nontemporal streaming kernels
-    (copy, read-only, write-only), torch's copy_ and the HIP runtime's
-    device-to-device memcpy, each timed as the median of HIP-event intervals."""
+    (copy with four and with one vector per thread, the planar copy of two
+    64 MiB planes into two as the transform streams them, read-only,
+    write-only), torch's copy_ and the HIP runtime's device-to-device memcpy,
+    each timed as the median of HIP-event intervals."""
     import ctypes
 
     import torch
@@ -455,6 +457,8 @@ def copy_ceiling(iters: int = MIN_ITERS, sets: int = 4):
         return fn
 
     out["nt_float4_copy"] = timed(probe(0), 2 * nbytes)
+    out["nt_float4_copy_one_vector_per_thread"] = timed(probe(4), 2 * nbytes)
+    out["nt_float4_planar_copy"] = timed(probe(3), 2 * nbytes)
     out["nt_float4_read"] = timed(probe(1), nbytes)
     out["nt_float4_write"] = timed(probe(2), nbytes)
     out["torch_copy"] = timed(lambda k: dst[k % sets].copy_(src[k % sets]), 2 * nbytes)

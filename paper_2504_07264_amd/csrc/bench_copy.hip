@@ -51,16 +51,52 @@ __global__ void __launch_bounds__(kThreads) stream_kernel(const v4f* __restrict_
     }
 }
 
+// The transform's streams: two source planes to two destination planes
+// (each n floats), VPP 16-byte vectors per plane per thread.
+template <int VPP>
+__global__ void __launch_bounds__(kThreads) planar_copy_kernel(const v4f* __restrict__ xr, const v4f* __restrict__ xi,
+                                                               v4f* __restrict__ yr, v4f* __restrict__ yi, int64_t nvec)
+{
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * (kThreads * VPP) + threadIdx.x;
+    v4f a[VPP], b[VPP];
+#pragma unroll
+    for (int k = 0; k < VPP; ++k) {
+        const int64_t i = base + k * kThreads;
+        const bool in = i < nvec;
+        a[k] = in ? __builtin_nontemporal_load(xr + i) : v4f{0.f, 0.f, 0.f, 0.f};
+        b[k] = in ? __builtin_nontemporal_load(xi + i) : v4f{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int k = 0; k < VPP; ++k) {
+        const int64_t i = base + k * kThreads;
+        if (i < nvec) {
+            __builtin_nontemporal_store(a[k], yr + i);
+            __builtin_nontemporal_store(b[k], yi + i);
+        }
+    }
+}
+
+// One 16-byte vector per thread (the fastest single-array copy measured).
+__global__ void __launch_bounds__(kThreads) copy1_kernel(const v4f* __restrict__ src, v4f* __restrict__ dst, int64_t nvec)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    if (i < nvec)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
 }  // namespace
 
 extern "C" {
 
 // Stream n_floats floats (a multiple of 4, 16-byte aligned pointers) on the
 // given hipStream_t.  mode 0 copies src to dst, 1 reads src, 2 writes dst;
-// sink: one float of device memory (mode 1).  Returns a hipError_t value.
+// 3 copies the two halves of src (two planes) to the two halves of dst, four
+// vectors per plane per thread, as the transform kernels stream them (n_floats
+// a multiple of 8); 4 copies src to dst with one vector per thread; sink: one
+// float of device memory (mode 1).  Returns a hipError_t value.
 int splitdft_bench_stream(const float* src, float* dst, int64_t n_floats, int mode, float* sink, void* stream)
 {
-    if (n_floats <= 0 || n_floats % 4 != 0 || mode < 0 || mode > 2)
+    if (n_floats <= 0 || n_floats % 4 != 0 || mode < 0 || mode > 4 || (mode == 3 && n_floats % 8 != 0))
         return static_cast<int>(hipErrorInvalidValue);
     if ((mode != 2 && (!src || reinterpret_cast<uintptr_t>(src) % 16 != 0)) ||
         (mode != 1 && (!dst || reinterpret_cast<uintptr_t>(dst) % 16 != 0)) || (mode == 1 && !sink))
@@ -73,6 +109,20 @@ int splitdft_bench_stream(const float* src, float* dst, int64_t n_floats, int mo
     const v4f* s = reinterpret_cast<const v4f*>(src);
     v4f* d = reinterpret_cast<v4f*>(dst);
     const dim3 grid(static_cast<unsigned>(blocks)), block(kThreads);
+    if (mode == 3) {
+        const int64_t half = nvec / 2;
+        const int64_t pblocks = (half + kThreads * 4 - 1) / (kThreads * 4);
+        hipLaunchKernelGGL(planar_copy_kernel<4>, dim3(static_cast<unsigned>(pblocks)), block, 0, st, s, s + half, d,
+                           d + half, half);
+        return static_cast<int>(hipGetLastError());
+    }
+    if (mode == 4) {
+        const int64_t blocks1 = (nvec + kThreads - 1) / kThreads;
+        if (blocks1 > INT_MAX)
+            return static_cast<int>(hipErrorInvalidValue);
+        hipLaunchKernelGGL(copy1_kernel, dim3(static_cast<unsigned>(blocks1)), block, 0, st, s, d, nvec);
+        return static_cast<int>(hipGetLastError());
+    }
     if (mode == 0)
         hipLaunchKernelGGL(stream_kernel<0>, grid, block, 0, st, s, d, nvec, sink);
     else if (mode == 1)
