@@ -108,7 +108,8 @@ typedef enum {
  * (a wait that times out ends the launch with undefined results). */
 /* Bit 24: evaluate through the decimation-in-frequency factorisation of
  * eq. (9), y_2N = S D^(1) W^(1) ... D^(m) W^(m) x_2N (stages m down to 1,
- * butterfly before rotation, the bit reversal last), FP32, n <= 2^14; results
+ * butterfly before rotation, the bit reversal last), FP32, every n (two
+ * passes from 2^15: stages m..9 on columns, then stages 8..1 on blocks); results
  * are bit-identical to those factors applied in that order with the
  * operation forms above. */
 #define SPLIT_DFT_DIF (1u << 24)

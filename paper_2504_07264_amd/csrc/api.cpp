@@ -332,15 +332,15 @@ split_dft_status split_dft_plan(split_dft_plan_t* out, int64_t n, int64_t batch,
     int count = 0, count2 = 0;
     const splitdft::Variant* list =
         dif ? splitdft::dif_variants_for(m, &count) : splitdft::variants_for(m, &count);
-    const splitdft::TwoPass* list2 = dif ? nullptr : splitdft::two_pass_for(m, &count2);
-    if (dif && count == 0)
-        return fail(SPLIT_DFT_ERR_UNSUPPORTED, "the decimation-in-frequency schedule supports n <= 2^14");
+    const splitdft::TwoPass* list2 = dif ? splitdft::dif_two_pass_for(m, &count2) : splitdft::two_pass_for(m, &count2);
+    if (dif && count == 0 && count2 == 0)
+        return fail(SPLIT_DFT_ERR_UNSUPPORTED, "no decimation-in-frequency schedule for n = " + std::to_string(n));
     const splitdft::Variant* v = nullptr;
     const splitdft::TwoPass* two = nullptr;
     if (vsel == 0) {
         if (mode != splitdft::kModeFP32 || count > 0)
             v = dif ? &list[0] : splitdft::default_variant(m, batch);
-        if (!dif && (m >= kTwoPassDefaultLog2N || !v))
+        if ((!dif && m >= kTwoPassDefaultLog2N) || !v)
             two = count2 > 0 ? &list2[0] : nullptr;
         if (two)
             v = nullptr;
@@ -569,6 +569,14 @@ split_dft_status split_dft_plan_describe(split_dft_plan_t plan, char* buf, size_
                           "two-pass fused a=%d: %d blocks / %d columns per tile, %d threads, lds=%d, "
                           "ring %d transforms per XCD",
                           t->a, t->c1, t->c2, t->threads1, t->lds1 > t->lds2 ? t->lds1 : t->lds2, t->slots);
+            return SPLIT_DFT_OK;
+        }
+        if (t->dif) {
+            std::snprintf(buf, len,
+                          "dif two-pass a=%d: pass1 %d columns/wg %d threads lds=%d gf=%d, pass2 %d blocks/wg %d "
+                          "threads lds=%d, chunk=%lld",
+                          t->a, t->c1, t->threads1, t->lds1, t->gf2 ? 1 : 0, t->c2, t->threads2, t->lds2,
+                          static_cast<long long>(plan->chunk));
             return SPLIT_DFT_OK;
         }
         std::snprintf(buf, len,

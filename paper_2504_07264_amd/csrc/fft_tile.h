@@ -214,8 +214,9 @@ __device__ __forceinline__ void blocks_out(float* dst, const float* lds, const C
     }
 }
 
-// Pass 2 output: natural positions lo + (p << A), along tile rows.
-template <class TC, class CS>
+// Pass 2 output: natural positions lo + (p << A), along tile rows
+// (nontemporal stores unless NT is false).
+template <class TC, class CS, bool NT = true>
 __device__ __forceinline__ void rows_out(float* dst, const float* lds, const CS& tc, int tid)
 {
     constexpr int C4 = TC::C / 4, RSTEP = TC::THREADS / C4;
@@ -226,7 +227,7 @@ __device__ __forceinline__ void rows_out(float* dst, const float* lds, const CS&
     for (int c = 0; c < TC::E / 4; ++c) {
         const int r = r0 + c * RSTEP;
         const float* s = lds + (4 * c4) * TC::SLOT + lds_index(r);
-        store4<true>(dst + (col + (r << TC::A)), v4f{s[0], s[TC::SLOT], s[2 * TC::SLOT], s[3 * TC::SLOT]});
+        store4<NT>(dst + (col + (r << TC::A)), v4f{s[0], s[TC::SLOT], s[2 * TC::SLOT], s[3 * TC::SLOT]});
     }
 }
 
@@ -328,6 +329,199 @@ __device__ __forceinline__ void tile_process(const Src& sr, const Src& si, float
             rows_out<TC, CS>(yi, area_i, tc, tid);
         }
     }
+}
+
+// ---- decimation in frequency, eq. (9), in two passes ---------------------
+// The stages run m down to 1 on the natural-order input, the bit reversal
+// last.  Split at a: stages m..a+1 act on bits m-1..a, so the positions
+// lo + (p << a) (lo < 2^a) form independent columns; this first pass has the
+// column geometry of a TileCfg with PASS 2 (natural layout on both sides:
+// columns read from the input, rows written to the workspace).  Stages a..1
+// act on blocks of 2^a consecutive positions (the block geometry of PASS 1);
+// position c 2^a + j is output rev_m(c 2^a + j) = rev_a(j) 2^(m-a) +
+// rev_(m-a)(c), so with the tile's blocks c = rev_(m-a)(k) for consecutive k
+// every output row rev_a(j) is a run of C contiguous floats.
+
+// Stages S+RP .. S+1 of eq. (9) for a group of 2^MA positions whose position p
+// is the transform's lo_g + (p << A): per stage, highest first, the butterfly
+// W^(i) (u + v, u - v), then the rotation D^(i) of the upper element by
+// omega^(i,q), q = lo_g + (ql << A) (the index mapping of stages()).
+template <int E, int LT, int S, int RP, class TW, int A>
+__device__ __forceinline__ void stages_dif_group(float (&vr)[E], float (&vi)[E], int t, const float2* __restrict__ tw,
+                                                 int lo_g)
+{
+#pragma unroll
+    for (int k = RP; k >= 1; --k) {
+        const int half = 1 << (k - 1);
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            if (u & half)
+                continue;
+            const int v = u + half;
+            const float ur = vr[u], ui = vi[u], wr = vr[v], wi = vi[v];
+            vr[u] = ur + wr;
+            vi[u] = ui + wi;
+            float dr = ur - wr, di = ui - wi;
+            if constexpr (S == 0 && A == 0) {
+                const int q = u & (half - 1);
+                if (q == 0) {
+                    // omega^(k,0) = I
+                } else if (2 * q == half) {
+                    const float tr = di;  // angle pi/2
+                    di = -dr;
+                    dr = tr;
+                } else {
+                    const float2 w = tw[half + q];
+                    rotate(dr, di, w.x, w.y);
+                }
+            } else {
+                const int qt = lo_g + ((t & ((1 << S) - 1)) << A);
+                const int qc = ((((u >> RP) << LT) & ((1 << S) - 1)) + ((u & (half - 1)) << S)) << A;
+                const float2 w = TW::get2(tw, A + S + k, qt, qc);
+                rotate(dr, di, w.x, w.y);
+            }
+            vr[v] = dr;
+            vi[v] = di;
+        }
+    }
+}
+
+// DIF passes P, P+1, ... of a group (exchange through the group's LDS slot,
+// SYNC_T as for later_passes), then the pass's stages.
+template <int M, int RB, int P, int E, class TW, int A, int SYNC_T>
+__device__ __forceinline__ void later_passes_dif_group(float (&vr)[E], float (&vi)[E], float* lr, int t,
+                                                       const float2* __restrict__ tw, int lo_g)
+{
+    if constexpr (P < PassD<M, RB, 0>::NP) {
+        constexpr int LT = M - RB;
+        using Prev = PassD<M, RB, P - 1>;
+        using Cur = PassD<M, RB, P>;
+        lds_put<E, LT, Prev::S, Prev::RP, Cur::S, Cur::RP>(vr, lr, t);
+        xsync<SYNC_T>();
+        lds_get<E, LT, Cur::S, Cur::RP>(vr, lr, t);
+        xsync<SYNC_T>();
+        lds_put<E, LT, Prev::S, Prev::RP, Cur::S, Cur::RP>(vi, lr, t);
+        xsync<SYNC_T>();
+        lds_get<E, LT, Cur::S, Cur::RP>(vi, lr, t);
+        xsync<SYNC_T>();
+        stages_dif_group<E, LT, Cur::S, Cur::RP, TW, A>(vr, vi, t, tw, lo_g);
+        later_passes_dif_group<M, RB, P + 1, E, TW, A, SYNC_T>(vr, vi, lr, t, tw, lo_g);
+    }
+}
+
+// Second DIF pass input: this thread's 16-byte vectors of one plane of the
+// tile's blocks (block rev_(m-a)(tile column i), contiguous in the workspace)
+// ...
+template <class TC, class CS, class Src>
+__device__ __forceinline__ void blocks_load(v4f (&r)[TC::E / 4], const Src& src, const CS& tc, int tid)
+{
+    constexpr int R4 = TC::R / 4;
+#pragma unroll
+    for (int c = 0; c < TC::E / 4; ++c) {
+        const int f4 = tid + c * TC::THREADS;
+        const int i = f4 / R4, p4 = f4 % R4;
+        const int blk = rev_bits(tile_col<TC, CS>(tc, i), TC::M - TC::A);
+        r[c] = src.load(blk * TC::R + 4 * p4);
+    }
+}
+
+// ... into the LDS slots: block position j of tile column i at lds_index(j).
+template <class TC>
+__device__ __forceinline__ void blocks_put(const v4f (&r)[TC::E / 4], float* lds, int tid)
+{
+    constexpr int R4 = TC::R / 4;
+#pragma unroll
+    for (int c = 0; c < TC::E / 4; ++c) {
+        const int f4 = tid + c * TC::THREADS;
+        const int i = f4 / R4, p4 = f4 % R4;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            lds[i * TC::SLOT + lds_index(4 * p4 + e)] = r[c][e];
+    }
+}
+
+// Second DIF pass output: output row r holds block position rev_a(r) of
+// every tile column, at r 2^(m-a) + (tile column).
+template <class TC, class CS>
+__device__ __forceinline__ void bitrev_rows_out(float* dst, const float* lds, const CS& tc, int tid)
+{
+    constexpr int C4 = TC::C / 4, RSTEP = TC::THREADS / C4;
+    const int c4 = tid % C4, r0 = tid / C4;
+    const int col = tile_col<TC, CS>(tc, 4 * c4);
+#pragma unroll
+    for (int c = 0; c < TC::E / 4; ++c) {
+        const int r = r0 + c * RSTEP;
+        const float* s = lds + (4 * c4) * TC::SLOT + lds_index(rev_bits(r, TC::MA));
+        store4<true>(dst + (r * (TC::N >> TC::A) + col), v4f{s[0], s[TC::SLOT], s[2 * TC::SLOT], s[3 * TC::SLOT]});
+    }
+}
+
+// One tile of a DIF pass: TC::PASS 2 is the first (columns of the input into
+// the workspace), TC::PASS 1 the second (workspace blocks into the output).
+// The group's positions sit in natural order in its LDS slot on the way in
+// and on the way out.
+template <class TC, class CS, class Src>
+__device__ __forceinline__ void tile_process_dif(const Src& sr, const Src& si, float* yr, float* yi,
+                                                 const float2* __restrict__ tw, const CS& tc, float* lds, int tid)
+{
+    static_assert(TC::SPLIT && TC::WSC == 0, "split-plane tiles, natural workspace layout");
+    constexpr int E = TC::E, LT = TC::LT, T = TC::T, C = TC::C;
+    using First = PassD<TC::MA, TC::RB, 0>;
+    using Last = PassD<TC::MA, TC::RB, First::NP - 1>;
+    const int g = TC::GF ? tid % C : tid >> LT;
+    const int t = TC::GF ? tid / C : tid & (T - 1);
+    float* lr = lds + g * TC::SLOT;
+
+    float vr[E], vi[E];
+    v4f pr[E / 4], pi[E / 4];
+    if constexpr (TC::PASS == 2) {
+        tile_load<TC, CS>(pr, sr, tc, tid);
+        tile_load<TC, CS>(pi, si, tc, tid);
+        tile_put<TC>(pr, lds, tid);
+    } else {
+        blocks_load<TC, CS>(pr, sr, tc, tid);
+        blocks_load<TC, CS>(pi, si, tc, tid);
+        blocks_put<TC>(pr, lds, tid);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < E; ++u)
+        vr[u] = lr[lds_index(position<LT, First::S, First::RP>(t, u))];
+    __syncthreads();
+    if constexpr (TC::PASS == 2)
+        tile_put<TC>(pi, lds, tid);
+    else
+        blocks_put<TC>(pi, lds, tid);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < E; ++u)
+        vi[u] = lr[lds_index(position<LT, First::S, First::RP>(t, u))];
+    __syncthreads();
+
+    const int lo_g = TC::PASS == 1 ? 0 : tile_col<TC, CS>(tc, g);
+    stages_dif_group<E, LT, First::S, First::RP, TwTable<0>, TC::TW_SHIFT>(vr, vi, t, tw, lo_g);
+    if constexpr (First::NP > 1)
+        later_passes_dif_group<TC::MA, TC::RB, 1, E, TwTable<0>, TC::TW_SHIFT, TC::GF ? 1024 : T>(vr, vi, lr, t, tw,
+                                                                                                 lo_g);
+
+    // natural position order in the slot, one plane at a time
+#pragma unroll
+    for (int u = 0; u < E; ++u)
+        lr[lds_index(position<LT, Last::S, Last::RP>(t, u))] = vr[u];
+    __syncthreads();
+    if constexpr (TC::PASS == 2)
+        rows_out<TC, CS, false>(yr, lds, tc, tid);
+    else
+        bitrev_rows_out<TC, CS>(yr, lds, tc, tid);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < E; ++u)
+        lr[lds_index(position<LT, Last::S, Last::RP>(t, u))] = vi[u];
+    __syncthreads();
+    if constexpr (TC::PASS == 2)
+        rows_out<TC, CS, false>(yi, lds, tc, tid);
+    else
+        bitrev_rows_out<TC, CS>(yi, lds, tc, tid);
 }
 
 // The same from plane pointers (nontemporal loads on pass 1's data side).

@@ -83,6 +83,48 @@ hipError_t launch_tile(const float* xr, const float* xi, float* yr, float* yi, c
     return hipGetLastError();
 }
 
+// A pass of the decimation-in-frequency two-pass schedule (TC::PASS 2: the
+// first, input columns into the workspace; TC::PASS 1: the second, workspace
+// blocks into the output in bit-reversed order).
+template <class TC>
+__global__ void __launch_bounds__(TC::THREADS)
+split_fft_tile_dif_kernel(const float* xr, const float* xi, float* yr, float* yi, const float2* __restrict__ tw,
+                          int tiles_per_transform, const int64_t* __restrict__ rows)
+{
+    __shared__ float lds[TC::LDS_WORDS];
+    const int64_t t = blockIdx.x / tiles_per_transform;
+    const int64_t wbase = t * TC::N;
+    const int64_t dbase = rows ? rows[t] : wbase;
+    const int64_t ibase = TC::PASS == 2 ? dbase : wbase;
+    const int64_t obase = TC::PASS == 2 ? wbase : dbase;
+    const TileCols<false> tc{static_cast<int>(blockIdx.x % tiles_per_transform) * TC::C};
+    tile_process_dif<TC>(PlaneSrc<TC::PASS == 2>{xr + ibase}, PlaneSrc<TC::PASS == 2>{xi + ibase}, yr + obase,
+                         yi + obase, tw, tc, lds, threadIdx.x);
+}
+
+template <class TC>
+hipError_t launch_tile_dif(const float* xr, const float* xi, float* yr, float* yi, const float2* tw, int64_t batch,
+                           const int64_t* rows, hipStream_t stream)
+{
+    const int64_t blocks = batch * TC::TILES;
+    if (blocks > INT_MAX)
+        return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((split_fft_tile_dif_kernel<TC>), dim3(static_cast<unsigned>(blocks)), dim3(TC::THREADS), 0,
+                       stream, xr, xi, yr, yi, tw, TC::TILES, rows);
+    return hipGetLastError();
+}
+
+// DIF two-pass schedule: C1 input columns per first-pass tile (lanes over
+// columns first when GF1), C2 blocks per second-pass tile.
+template <int M, int A, int RB1, int C1, bool GF1, int RB2, int C2>
+constexpr TwoPass make_two_pass_dif()
+{
+    using P1 = TileCfg<M, A, 2, RB1, C1, true, GF1, 0>;
+    using P2 = TileCfg<M, A, 1, RB2, C2, true, false, 0>;
+    return TwoPass{M,     A,     C1,    C2, P1::THREADS, P2::THREADS, 4 * P1::LDS_WORDS, 4 * P2::LDS_WORDS,
+                   GF1,   &launch_tile_dif<P1>, &launch_tile_dif<P2>, false, nullptr, 0, true};
+}
+
 // Polls per wait of the fused schedule before it gives up (each poll sleeps
 // up to about 0.4 us after a load from L2: seconds in all).
 constexpr int kXcdPollLimit = 1 << 22;
@@ -177,9 +219,24 @@ const TwoPass kTwoPass16[] = {make_two_pass<16, 8, 4, 32, true, 4, 32, true, tru
 
 }  // namespace
 
+//                                              M   A  RB1 C1 GF1 RB2 C2
+const TwoPass kDifTwoPass15[] = {make_two_pass_dif<15, 8, 4, 64, true, 4, 32>(),
+                                 make_two_pass_dif<15, 8, 4, 32, true, 4, 32>()};
+const TwoPass kDifTwoPass16[] = {make_two_pass_dif<16, 8, 4, 32, true, 4, 32>(),
+                                 make_two_pass_dif<16, 8, 4, 64, true, 4, 32>()};
+
 size_t fused_workspace_bytes(const TwoPass* t)
 {
     return static_cast<size_t>(xcd_ring_floats(t->m, t->slots)) * sizeof(float) + xcd_control_bytes();
+}
+
+const TwoPass* dif_two_pass_for(int m, int* count)
+{
+    switch (m) {
+    case 15: *count = static_cast<int>(sizeof(kDifTwoPass15) / sizeof(kDifTwoPass15[0])); return kDifTwoPass15;
+    case 16: *count = static_cast<int>(sizeof(kDifTwoPass16) / sizeof(kDifTwoPass16[0])); return kDifTwoPass16;
+    default: *count = 0; return nullptr;
+    }
 }
 
 const TwoPass* two_pass_for(int m, int* count)

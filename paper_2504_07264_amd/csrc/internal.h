@@ -66,6 +66,9 @@ struct TwoPass {
     hipError_t (*fused)(const float* xr, const float* xi, float* yr, float* yi, const float2* tw, int64_t batch,
                         const int64_t* rows, float* ws, hipStream_t stream) = nullptr;
     int slots = 0;
+    // decimation in frequency (eq. (9)): pass 1 runs stages m..a+1 on c1
+    // columns per workgroup, pass 2 stages a..1 on c2 blocks
+    bool dif = false;
 };
 
 // Workspace bytes of a fused two-pass schedule (ring and control block).
@@ -74,8 +77,10 @@ size_t fused_workspace_bytes(const TwoPass* t);
 // Offset in floats, modulo 32, of a plane pointer from a 128-byte line.
 inline int line_offset(const float* p) { return static_cast<int>((reinterpret_cast<uintptr_t>(p) >> 2) & 31); }
 
-// Compiled two-pass schedules for length 2^m (count returned through *count).
+// Compiled two-pass schedules for length 2^m (count returned through *count);
+// dif_two_pass_for: those of the decimation-in-frequency order.
 const TwoPass* two_pass_for(int m, int* count);
+const TwoPass* dif_two_pass_for(int m, int* count);
 
 // ---- grouped (ragged, mixed-length) execution --------------------------
 constexpr int kManyThreads = 512;         // workgroup size of the grouped kernel

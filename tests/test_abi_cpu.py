@@ -70,7 +70,10 @@ def test_matrix_core_modes_need_n256(L, n, mode):
 
 
 def test_dif_flag_domain(L):
-    assert _plan(L, 1 << 15, 4, binding.DIF)[0] == 6
+    # every length has a DIF schedule (two passes from 2^15); selectors beyond
+    # the compiled ones, matrix-core modes and unknown bits are rejected
+    assert _plan(L, 1 << 15, 4, binding.DIF | binding.variant_flag(200))[0] == 6
+    assert _plan(L, 1 << 16, 4, binding.DIF | binding.variant_flag(200))[0] == 6
     assert _plan(L, 256, 4, binding.DIF | binding.BF16X2)[0] == 6
     assert _plan(L, 256, 4, binding.DIF | (1 << 25))[0] == 6
 

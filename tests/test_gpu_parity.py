@@ -215,7 +215,8 @@ def test_adjoint_full_size_n4096():
 # small batches (one block per workgroup) and batches that give every
 # resident workgroup of a persistent schedule several blocks
 @pytest.mark.parametrize("n,batch,dif", [(1024, 37, False), (1024, 16387, False), (64, 262147, False),
-                                         (8192, 2051, False), (1024, 16387, True), (16384, 1027, True)])
+                                         (8192, 2051, False), (1024, 16387, True), (16384, 1027, True),
+                                         (32768, 41, True), (65536, 300, True)])
 def test_in_place_and_swapped_planes(n, batch, dif):
     xr, xi = inputs.draw_planes(n, batch, "normal", 7)
     mirror = oracle.split_fft_dif_f32 if dif else oracle.split_fft_f32
@@ -503,7 +504,7 @@ def all_dif_variants(m):
     return out
 
 
-@pytest.mark.parametrize("m", range(0, 15))
+@pytest.mark.parametrize("m", range(0, 17))
 def test_dif_every_length(m):
     n = 1 << m
     batch = max(3, min(1000, (1 << 19) // n)) | 1
