@@ -203,20 +203,20 @@ split_fft_xcd_kernel(const float* xr, const float* xi, float* yr, float* yi, con
         const int64_t dbase = rows ? rows[g] : static_cast<int64_t>(g) * N;
         float* wr = ring + (static_cast<int64_t>(x) * slots + slot) * (2 * N);
         float* wi = wr + N;
-        {
-            if constexpr (ROT) {
-                const int rot = static_cast<int>(((reinterpret_cast<uintptr_t>(xr) >> 2) + dbase) & 31);
-                tile_process<P1>(PlaneSrc<true>{xr + dbase}, PlaneSrc<true>{xi + dbase}, wr, wi, tw,
-                                 TileCols<true>{r * P1::C, rot}, lds, lane_tid, NoHook{});
-            } else {
-                tile_process<P1>(PlaneSrc<true>{xr + dbase}, PlaneSrc<true>{xi + dbase}, wr, wi, tw,
-                                 TileCols<false>{r * P1::C}, lds, lane_tid, NoHook{});
-            }
-            __builtin_amdgcn_s_waitcnt(0);  // this thread's stores acknowledged by L2
-            __syncthreads();
-            if (tid == 0)
-                __hip_atomic_fetch_add(&ctl->written[x][slot][0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // pass-1 tile r into the slot
+        if constexpr (ROT) {
+            const int rot = static_cast<int>(((reinterpret_cast<uintptr_t>(xr) >> 2) + dbase) & 31);
+            tile_process<P1>(PlaneSrc<true>{xr + dbase}, PlaneSrc<true>{xi + dbase}, wr, wi, tw,
+                             TileCols<true>{r * P1::C, rot}, lds, lane_tid, NoHook{});
+        } else {
+            tile_process<P1>(PlaneSrc<true>{xr + dbase}, PlaneSrc<true>{xi + dbase}, wr, wi, tw,
+                             TileCols<false>{r * P1::C}, lds, lane_tid, NoHook{});
         }
+        __builtin_amdgcn_s_waitcnt(0);  // this thread's stores acknowledged by L2
+        __syncthreads();
+        if (tid == 0)
+            __hip_atomic_fetch_add(&ctl->written[x][slot][0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // the transform's other pass-1 tiles
         if (wave0) {
             const bool w = xcd_wait_geq(&ctl->written[x][slot][0], T1 * (gen + 1), ctl, limit);
             if (tid == 0)
@@ -224,15 +224,15 @@ split_fft_xcd_kernel(const float* xr, const float* xi, float* yr, float* yi, con
         }
         __syncthreads();
         ok &= __builtin_amdgcn_readfirstlane(s_word);
-        {
-            int* gathered = &ctl->gathered[x][slot][0];
-            auto release = [gathered, tid]() {
-                if (tid == 0)
-                    __hip_atomic_fetch_add(gathered, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            };
-            tile_process<P2>(L2Src{plane_rsrc(wr, N)}, L2Src{plane_rsrc(wi, N)}, yr + dbase, yi + dbase, tw,
-                             TileCols<false>{r * P2::C}, lds, lane_tid, release);
-        }
+        // pass-2 tile r out of the slot, which is released as soon as its
+        // loads have been consumed
+        int* gathered = &ctl->gathered[x][slot][0];
+        auto release = [gathered, tid]() {
+            if (tid == 0)
+                __hip_atomic_fetch_add(gathered, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        };
+        tile_process<P2>(L2Src{plane_rsrc(wr, N)}, L2Src{plane_rsrc(wi, N)}, yr + dbase, yi + dbase, tw,
+                         TileCols<false>{r * P2::C}, lds, lane_tid, release);
     }
     if (!ok && tid == 0)
         atomicAdd(&ctl->failed, 1);
