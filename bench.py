@@ -84,16 +84,17 @@ TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "split_fft_n1024_b16384_hbm_tra
 
 
 def kernel_source_hash() -> str:
-    """sha256 of the forward kernel's source with comments and blank lines
+    """sha256 of the forward kernel's device source (fft_lds.hip, then the
+    stage code it includes, fft_device.h) with comments and blank lines
     removed (a comment edit does not invalidate a measurement)."""
     import re
 
-    p = os.path.join(ROOT, "paper_2504_07264_amd", "csrc", "fft_lds.hip")
-    with open(p) as f:
-        text = f.read()
-    lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines()]
-    code = "\n".join(ln for ln in lines if ln.strip())
-    return hashlib.sha256(code.encode()).hexdigest()
+    code = []
+    for name in ("fft_lds.hip", "fft_device.h"):
+        with open(os.path.join(ROOT, "paper_2504_07264_amd", "csrc", name)) as f:
+            lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in f.read().splitlines()]
+        code.append("\n".join(ln for ln in lines if ln.strip()))
+    return hashlib.sha256("\n".join(code).encode()).hexdigest()
 
 
 def measured_traffic():
