@@ -5,8 +5,8 @@ stage 8, Section III).  Bit-exact against the FP32 mirror of eq. (6) over
 batches that reuse every ring slot several times, forward and adjoint, on
 repeated launches, in place, on planes off a 128-byte line (rotated pass-1
 tiles), for batches smaller than the number of XCDs, through a caller
-workspace and through the no-allocation entry point; guard words around the
-outputs."""
+workspace, through the no-allocation entry point and replayed from a HIP
+graph; guard words around the outputs."""
 import sys
 
 import numpy as np
@@ -125,3 +125,43 @@ def test_fused_caller_workspace_and_no_allocation(m):
             p.exec_noalloc(dr, di, zr, zi)
             torch.cuda.synchronize()
             assert_bit_exact(zr, zi, mr, mi, "no-allocation entry point, call %d" % rep)
+
+
+@pytest.mark.parametrize("m,batch", [(15, 77), (16, 40)])
+def test_fused_captured_in_a_graph(m, batch):
+    # the control block is cleared by a kernel, not a memset, so the fused
+    # launch can be captured: every replay must equal the eager result, with
+    # other work and synchronisations between the replays
+    n = 1 << m
+    flags = fused_flags(m)
+    xr, xi = inputs.draw_planes(n, batch, "normal", 950 + m)
+    say("  fused graph capture n=%d batch=%d" % (n, batch))
+    with Plan(n, batch, flags) as p:
+        ws = torch.empty((p.workspace_bytes() + 3) // 4, device="cuda")
+        ar, ai = xr.cuda(), xi.cuda()
+        er, ei = p.exec(ar, ai, workspace=ws)
+        gr, gi = p.adjoint(er, ei, workspace=ws)
+        torch.cuda.synchronize()
+        yr, yi = torch.empty_like(ar), torch.empty_like(ai)
+        hr, hi = torch.empty_like(ar), torch.empty_like(ai)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):  # warm-up on the capturing stream
+            p.exec(ar, ai, yr, yi, workspace=ws)
+            p.adjoint(yr, yi, hr, hi, workspace=ws)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            p.exec(ar, ai, yr, yi, workspace=ws)
+            p.adjoint(yr, yi, hr, hi, workspace=ws)
+        for k in range(3):
+            for t in (yr, yi, hr, hi):
+                t.fill_(float("nan"))
+            ws.fill_(float("nan"))  # garbage in the control block and the ring
+            torch.cuda.synchronize()
+            graph.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(yr, er) and torch.equal(yi, ei), "replay %d forward" % k
+            assert torch.equal(hr, gr) and torch.equal(hi, gi), "replay %d adjoint" % k
+        del graph
