@@ -220,10 +220,14 @@ const TwoPass kTwoPass16[] = {make_two_pass<16, 8, 4, 32, true, 4, 32, true, tru
 }  // namespace
 
 //                                              M   A  RB1 C1 GF1 RB2 C2
+// (swept: 128 columns or lanes over rows first in the first pass, 64 blocks in
+// the second at 2^16, or 16 columns at 2^16, measured 2-30% slower)
 const TwoPass kDifTwoPass15[] = {make_two_pass_dif<15, 8, 4, 64, true, 4, 32>(),
+                                 make_two_pass_dif<15, 8, 4, 64, true, 4, 16>(),
                                  make_two_pass_dif<15, 8, 4, 32, true, 4, 32>()};
 const TwoPass kDifTwoPass16[] = {make_two_pass_dif<16, 8, 4, 32, true, 4, 32>(),
-                                 make_two_pass_dif<16, 8, 4, 64, true, 4, 32>()};
+                                 make_two_pass_dif<16, 8, 4, 64, true, 4, 32>(),
+                                 make_two_pass_dif<16, 8, 4, 32, true, 4, 16>()};
 
 size_t fused_workspace_bytes(const TwoPass* t)
 {
