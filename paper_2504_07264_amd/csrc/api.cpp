@@ -574,9 +574,9 @@ split_dft_status split_dft_plan_describe(split_dft_plan_t plan, char* buf, size_
         if (t->dif) {
             std::snprintf(buf, len,
                           "dif two-pass a=%d: pass1 %d columns/wg %d threads lds=%d gf=%d, pass2 %d blocks/wg %d "
-                          "threads lds=%d, chunk=%lld",
+                          "threads lds=%d ws=%s, chunk=%lld",
                           t->a, t->c1, t->threads1, t->lds1, t->gf2 ? 1 : 0, t->c2, t->threads2, t->lds2,
-                          static_cast<long long>(plan->chunk));
+                          t->wst ? "tiled" : "natural", static_cast<long long>(plan->chunk));
             return SPLIT_DFT_OK;
         }
         std::snprintf(buf, len,

@@ -456,15 +456,70 @@ __device__ __forceinline__ void bitrev_rows_out(float* dst, const float* lds, co
     }
 }
 
+// Tiled DIF workspace (WSX > 0): with C1 columns per first-pass tile and C2
+// blocks per second-pass tile, row p = rev_(m-a)(k) of column lo sits at
+//     (k / C2) (C2 2^a) + (lo / C1) (C2 C1) + (k mod C2) C1 + lo mod C1,
+// each intersection of a first-pass and a second-pass tile contiguous: a
+// second-pass tile (C2 consecutive k) reads one run of C2 2^a floats, and a
+// first-pass tile writes runs of C2 C1 floats.
+
+// First-pass output into the tiled workspace (C2: the second pass's tile width).
+template <class TC, class CS, int C2>
+__device__ __forceinline__ void dif_tiled_rows_out(float* dst, const float* lds, const CS& tc, int tid)
+{
+    constexpr int C1 = TC::C, C4 = C1 / 4, RSTEP = TC::THREADS / C4;
+    static_assert(TC::PASS == 2 && (1 << TC::MA) % C2 == 0, "first DIF pass, whole second-pass tiles");
+    const int c4 = tid % C4, r0 = tid / C4;
+    const int t1 = tc.col0 / C1;
+#pragma unroll
+    for (int c = 0; c < TC::E / 4; ++c) {
+        const int k = r0 + c * RSTEP;  // rows in bit-reversed order
+        const float* s = lds + (4 * c4) * TC::SLOT + lds_index(rev_bits(k, TC::MA));
+        const int off = (k / C2) * (C2 << TC::A) + t1 * (C2 * C1) + (k % C2) * C1 + 4 * c4;
+        store4<false>(dst + off, v4f{s[0], s[TC::SLOT], s[2 * TC::SLOT], s[3 * TC::SLOT]});
+    }
+}
+
+// Second-pass input from the tiled workspace: the tile's run, this thread's
+// 16-byte vectors ...
+template <class TC, class CS, class Src>
+__device__ __forceinline__ void dif_tiled_blocks_load(v4f (&r)[TC::E / 4], const Src& src, const CS& tc, int tid)
+{
+    static_assert(TC::PASS == 1, "second DIF pass");
+    const int base = (tc.col0 / TC::C) * (TC::C * TC::R);
+#pragma unroll
+    for (int c = 0; c < TC::E / 4; ++c)
+        r[c] = src.load(base + 4 * (tid + c * TC::THREADS));
+}
+
+// ... into the LDS slots (C1: the first pass's tile width): block k of the
+// tile (slot k mod C2) at position lo.
+template <class TC, int C1>
+__device__ __forceinline__ void dif_tiled_blocks_put(const v4f (&r)[TC::E / 4], float* lds, int tid)
+{
+    constexpr int C2 = TC::C;
+    static_assert(TC::R % C1 == 0 && C1 % 4 == 0, "whole first-pass tiles");
+#pragma unroll
+    for (int c = 0; c < TC::E / 4; ++c) {
+        const int f = 4 * (tid + c * TC::THREADS);
+        const int t1 = f / (C2 * C1), rem = f % (C2 * C1);
+        const int i = rem / C1, lo = t1 * C1 + rem % C1;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            lds[i * TC::SLOT + lds_index(lo + e)] = r[c][e];
+    }
+}
+
 // One tile of a DIF pass: TC::PASS 2 is the first (columns of the input into
 // the workspace), TC::PASS 1 the second (workspace blocks into the output).
-// The group's positions sit in natural order in its LDS slot on the way in
-// and on the way out.
-template <class TC, class CS, class Src>
+// WSX: the other pass's tile width for the tiled workspace layout, 0 for
+// natural position order.  The group's positions sit in natural order in its
+// LDS slot on the way in and on the way out.
+template <class TC, class CS, int WSX, class Src>
 __device__ __forceinline__ void tile_process_dif(const Src& sr, const Src& si, float* yr, float* yi,
                                                  const float2* __restrict__ tw, const CS& tc, float* lds, int tid)
 {
-    static_assert(TC::SPLIT && TC::WSC == 0, "split-plane tiles, natural workspace layout");
+    static_assert(TC::SPLIT && TC::WSC == 0, "split-plane tiles (the DIF layouts are chosen by WSX)");
     constexpr int E = TC::E, LT = TC::LT, T = TC::T, C = TC::C;
     using First = PassD<TC::MA, TC::RB, 0>;
     using Last = PassD<TC::MA, TC::RB, First::NP - 1>;
@@ -478,6 +533,10 @@ __device__ __forceinline__ void tile_process_dif(const Src& sr, const Src& si, f
         tile_load<TC, CS>(pr, sr, tc, tid);
         tile_load<TC, CS>(pi, si, tc, tid);
         tile_put<TC>(pr, lds, tid);
+    } else if constexpr (WSX > 0) {
+        dif_tiled_blocks_load<TC, CS>(pr, sr, tc, tid);
+        dif_tiled_blocks_load<TC, CS>(pi, si, tc, tid);
+        dif_tiled_blocks_put<TC, WSX>(pr, lds, tid);
     } else {
         blocks_load<TC, CS>(pr, sr, tc, tid);
         blocks_load<TC, CS>(pi, si, tc, tid);
@@ -490,6 +549,8 @@ __device__ __forceinline__ void tile_process_dif(const Src& sr, const Src& si, f
     __syncthreads();
     if constexpr (TC::PASS == 2)
         tile_put<TC>(pi, lds, tid);
+    else if constexpr (WSX > 0)
+        dif_tiled_blocks_put<TC, WSX>(pi, lds, tid);
     else
         blocks_put<TC>(pi, lds, tid);
     __syncthreads();
@@ -509,7 +570,9 @@ __device__ __forceinline__ void tile_process_dif(const Src& sr, const Src& si, f
     for (int u = 0; u < E; ++u)
         lr[lds_index(position<LT, Last::S, Last::RP>(t, u))] = vr[u];
     __syncthreads();
-    if constexpr (TC::PASS == 2)
+    if constexpr (TC::PASS == 2 && WSX > 0)
+        dif_tiled_rows_out<TC, CS, WSX>(yr, lds, tc, tid);
+    else if constexpr (TC::PASS == 2)
         rows_out<TC, CS, false>(yr, lds, tc, tid);
     else
         bitrev_rows_out<TC, CS>(yr, lds, tc, tid);
@@ -518,7 +581,9 @@ __device__ __forceinline__ void tile_process_dif(const Src& sr, const Src& si, f
     for (int u = 0; u < E; ++u)
         lr[lds_index(position<LT, Last::S, Last::RP>(t, u))] = vi[u];
     __syncthreads();
-    if constexpr (TC::PASS == 2)
+    if constexpr (TC::PASS == 2 && WSX > 0)
+        dif_tiled_rows_out<TC, CS, WSX>(yi, lds, tc, tid);
+    else if constexpr (TC::PASS == 2)
         rows_out<TC, CS, false>(yi, lds, tc, tid);
     else
         bitrev_rows_out<TC, CS>(yi, lds, tc, tid);

@@ -86,7 +86,7 @@ hipError_t launch_tile(const float* xr, const float* xi, float* yr, float* yi, c
 // A pass of the decimation-in-frequency two-pass schedule (TC::PASS 2: the
 // first, input columns into the workspace; TC::PASS 1: the second, workspace
 // blocks into the output in bit-reversed order).
-template <class TC>
+template <class TC, int WSX>
 __global__ void __launch_bounds__(TC::THREADS)
 split_fft_tile_dif_kernel(const float* xr, const float* xi, float* yr, float* yi, const float2* __restrict__ tw,
                           int tiles_per_transform, const int64_t* __restrict__ rows)
@@ -98,31 +98,33 @@ split_fft_tile_dif_kernel(const float* xr, const float* xi, float* yr, float* yi
     const int64_t ibase = TC::PASS == 2 ? dbase : wbase;
     const int64_t obase = TC::PASS == 2 ? wbase : dbase;
     const TileCols<false> tc{static_cast<int>(blockIdx.x % tiles_per_transform) * TC::C};
-    tile_process_dif<TC>(PlaneSrc<TC::PASS == 2>{xr + ibase}, PlaneSrc<TC::PASS == 2>{xi + ibase}, yr + obase,
-                         yi + obase, tw, tc, lds, threadIdx.x);
+    tile_process_dif<TC, TileCols<false>, WSX>(PlaneSrc<TC::PASS == 2>{xr + ibase}, PlaneSrc<TC::PASS == 2>{xi + ibase},
+                                               yr + obase, yi + obase, tw, tc, lds, threadIdx.x);
 }
 
-template <class TC>
+template <class TC, int WSX>
 hipError_t launch_tile_dif(const float* xr, const float* xi, float* yr, float* yi, const float2* tw, int64_t batch,
                            const int64_t* rows, hipStream_t stream)
 {
     const int64_t blocks = batch * TC::TILES;
     if (blocks > INT_MAX)
         return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((split_fft_tile_dif_kernel<TC>), dim3(static_cast<unsigned>(blocks)), dim3(TC::THREADS), 0,
-                       stream, xr, xi, yr, yi, tw, TC::TILES, rows);
+    hipLaunchKernelGGL((split_fft_tile_dif_kernel<TC, WSX>), dim3(static_cast<unsigned>(blocks)), dim3(TC::THREADS),
+                       0, stream, xr, xi, yr, yi, tw, TC::TILES, rows);
     return hipGetLastError();
 }
 
 // DIF two-pass schedule: C1 input columns per first-pass tile (lanes over
-// columns first when GF1), C2 blocks per second-pass tile.
-template <int M, int A, int RB1, int C1, bool GF1, int RB2, int C2>
+// columns first when GF1), C2 blocks per second-pass tile; WST: the tiled
+// workspace layout (see tile_process_dif), else natural position order.
+template <int M, int A, int RB1, int C1, bool GF1, int RB2, int C2, bool WST = true>
 constexpr TwoPass make_two_pass_dif()
 {
     using P1 = TileCfg<M, A, 2, RB1, C1, true, GF1, 0>;
     using P2 = TileCfg<M, A, 1, RB2, C2, true, false, 0>;
-    return TwoPass{M,     A,     C1,    C2, P1::THREADS, P2::THREADS, 4 * P1::LDS_WORDS, 4 * P2::LDS_WORDS,
-                   GF1,   &launch_tile_dif<P1>, &launch_tile_dif<P2>, false, nullptr, 0, true};
+    return TwoPass{M,     A,   C1,  C2, P1::THREADS, P2::THREADS, 4 * P1::LDS_WORDS, 4 * P2::LDS_WORDS,
+                   GF1,   &launch_tile_dif<P1, WST ? C2 : 0>, &launch_tile_dif<P2, WST ? C1 : 0>,
+                   WST,   nullptr, 0, true};
 }
 
 // Polls per wait of the fused schedule before it gives up (each poll sleeps
@@ -223,9 +225,11 @@ const TwoPass kTwoPass16[] = {make_two_pass<16, 8, 4, 32, true, 4, 32, true, tru
 // (swept: 128 columns or lanes over rows first in the first pass, 64 blocks in
 // the second at 2^16, or 16 columns at 2^16, measured 2-30% slower)
 const TwoPass kDifTwoPass15[] = {make_two_pass_dif<15, 8, 4, 64, true, 4, 32>(),
+                                 make_two_pass_dif<15, 8, 4, 64, true, 4, 32, false>(),
                                  make_two_pass_dif<15, 8, 4, 64, true, 4, 16>(),
                                  make_two_pass_dif<15, 8, 4, 32, true, 4, 32>()};
 const TwoPass kDifTwoPass16[] = {make_two_pass_dif<16, 8, 4, 32, true, 4, 32>(),
+                                 make_two_pass_dif<16, 8, 4, 32, true, 4, 32, false>(),
                                  make_two_pass_dif<16, 8, 4, 64, true, 4, 32>(),
                                  make_two_pass_dif<16, 8, 4, 32, true, 4, 16>()};
 
