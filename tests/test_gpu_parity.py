@@ -537,3 +537,24 @@ def test_plan_info_and_describe():
         mi = mp.info()
         assert mi["count"] == 3 and mi["points"] == 16 + (1 << 15) + 64
         assert mi["workgroups"] > 0 and mi["items"] >= 1 and mi["workspace_bytes"] >= (1 << 15) * 2 * 4
+
+
+@pytest.mark.parametrize("m,batch", [(15, 300), (16, 131)])
+def test_dif_two_pass_workspace_paths(m, batch):
+    # the DIF two-pass schedule through a caller workspace and through the
+    # no-allocation entry point (whose static array holds fewer transforms than
+    # the batch: several chunks), bit-exact against the DIF mirror of eq. (9)
+    n = 1 << m
+    xr, xi = inputs.draw_planes(n, batch, "normal", 3100 + m)
+    mr, mi = oracle.split_fft_dif_f32(xr.numpy(), xi.numpy())
+    with Plan(n, batch, binding.DIF) as p:
+        say("  dif workspace paths n=%d batch=%d %s" % (n, batch, p.describe()))
+        dr, di = xr.cuda(), xi.cuda()
+        ws = torch.full(((p.workspace_bytes() + 3) // 4,), float("nan"), device="cuda")
+        yr, yi = p.exec(dr, di, workspace=ws)
+        torch.cuda.synchronize()
+        assert_bit_exact(to_np(yr), to_np(yi), mr, mi)
+        zr, zi = torch.empty_like(dr), torch.empty_like(di)
+        p.exec_noalloc(dr, di, zr, zi)
+        torch.cuda.synchronize()
+        assert_bit_exact(to_np(zr), to_np(zi), mr, mi)
