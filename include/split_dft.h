@@ -194,17 +194,19 @@ split_dft_status split_dft_exec_adjoint_ws(split_dft_plan_t plan, const float *x
  * allocation of any kind; the plan (created beforehand, which allocates) and
  * the caller's inputs and outputs are used as by split_dft_exec, with the same
  * argument rules and bit-identical results.  Two-pass plans run in equal
- * chunks of at most SPLIT_DFT_NOALLOC_SCRATCH_BYTES / (8 n) transforms; other
- * plans use no scratch.  A transform whose intermediate (8 n bytes) exceeded
- * the array would be rejected with SPLIT_DFT_ERR_UNSUPPORTED (no supported
- * length does).
+ * chunks of at most SPLIT_DFT_NOALLOC_SCRATCH_BYTES / (8 n) transforms; a plan
+ * on the fused two-pass schedule keeps its ring and control block there (32 MiB
+ * at most) and runs the whole batch at once; other plans use no scratch.  A
+ * transform whose intermediate (8 n bytes) exceeded the array would be
+ * rejected with SPLIT_DFT_ERR_UNSUPPORTED (no supported length does).
  *
  * Each GPU holds its own copy of the array from the library's first use on it
  * until the process ends; its device address is looked up once per device,
  * when a two-pass plan is created or at the first call.  Every call on one
  * GPU uses that GPU's one array: calls that overlap in time on one GPU
  * (different streams or threads, with any plans) race on it and give wrong
- * results.  Nothing in the array needs clearing between calls.
+ * results.  Nothing in the array needs clearing between calls (the fused
+ * schedule clears its own control block with a kernel on the call's stream).
  */
 #define SPLIT_DFT_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
 split_dft_status split_dft_exec_noalloc(split_dft_plan_t plan, const float *xr, const float *xi,
