@@ -176,8 +176,9 @@ hipError_t launch_xcd(const float* xr, const float* xi, float* yr, float* yi, co
         grid = resident;
     if (resident < least)
         return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(xcd_control_clear, dim3(1), dim3(256), 0, stream, reinterpret_cast<int*>(ctl),
-                       static_cast<int>(sizeof(XcdControl) / sizeof(int)));
+    static_assert(xcd_control_bytes() % 16 == 0, "whole 16-byte words");
+    hipLaunchKernelGGL(xcd_control_clear, dim3(4), dim3(256), 0, stream, reinterpret_cast<float4*>(ctl),
+                       static_cast<int>(xcd_control_bytes() / 16));
     hipLaunchKernelGGL(kernel, dim3(static_cast<unsigned>(grid)), dim3(P1::THREADS), 0, stream, xr, xi, yr, yi, tw,
                        batch, rows, ring, ctl, SLOTS, kXcdPollLimit);
     return hipGetLastError();

@@ -238,10 +238,11 @@ split_fft_xcd_kernel(const float* xr, const float* xi, float* yr, float* yi, con
         atomicAdd(&ctl->failed, 1);
 }
 
-__global__ void __launch_bounds__(256) xcd_control_clear(int* ctl, int words)
+// Zeroes the control block (vec4s 16-byte words, the block's rounded size).
+__global__ void __launch_bounds__(256) xcd_control_clear(float4* ctl, int vec4s)
 {
-    for (int i = threadIdx.x; i < words; i += 256)
-        ctl[i] = 0;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < vec4s; i += gridDim.x * 256)
+        ctl[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
 }  // namespace
