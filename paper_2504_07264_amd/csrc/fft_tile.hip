@@ -203,7 +203,10 @@ constexpr TwoPass make_two_pass()
 const TwoPass kTwoPass14[] = {make_two_pass<14, 8, 4, 32, true, 4, 128, true, true, true>(),
                               make_two_pass<14, 8, 4, 32, true, 4, 64, true, true, true>(),
                               make_two_pass<14, 8, 4, 32, true, 4, 32, true, true>()};
-// the last entries of the 2^15 and 2^16 lists: both passes in one launch
+// (split at stage 7 at 2^15 and at stage 9 at 2^16, appended after the fused
+// entries: within 1-2% of the stage-8 defaults; 16 blocks per pass-1 tile at
+// stage 9 and a stage-7 split at 2^16 measured 20-30% slower)
+// the fused entries of the 2^15 and 2^16 lists: both passes in one launch
 // through a ring of 12 (2^15, 3 MiB) or 8 (2^16, 4 MiB) transforms per XCD, the
 // fastest ring sizes measured (112 / 110 us per 2^24 points against 90 / 92
 // for the separate passes, so not the default)
@@ -212,13 +215,16 @@ const TwoPass kTwoPass15[] = {make_two_pass<15, 8, 4, 32, true, 4, 64, true, tru
                               make_two_pass<15, 8, 4, 32, true, 4, 128, true, true, true>(),
                               make_two_pass<15, 8, 4, 32, true, 4, 32, true, true>(),
                               make_two_pass<15, 8, 4, 16, false, 4, 32, false>(),
-                              make_two_pass<15, 8, 4, 32, true, 4, 64, true, true, true, 12>()};
+                              make_two_pass<15, 8, 4, 32, true, 4, 64, true, true, true, 12>(),
+                              make_two_pass<15, 7, 4, 64, true, 4, 32, true, true, true>(),
+                              make_two_pass<15, 7, 4, 32, true, 4, 32, true, true, true>()};
 const TwoPass kTwoPass16[] = {make_two_pass<16, 8, 4, 32, true, 4, 32, true, true, true>(),
                               make_two_pass<16, 8, 4, 64, true, 4, 32, true, true, true>(),
                               make_two_pass<16, 8, 4, 32, true, 4, 64, true, true, true>(),
                               make_two_pass<16, 8, 4, 32, true, 4, 32, true, true>(),
                               make_two_pass<16, 8, 4, 16, false, 4, 16, false>(),
-                              make_two_pass<16, 8, 4, 32, true, 4, 32, true, true, true, 8>()};
+                              make_two_pass<16, 8, 4, 32, true, 4, 32, true, true, true, 8>(),
+                              make_two_pass<16, 9, 4, 32, true, 4, 64, true, true, true>()};
 
 }  // namespace
 
