@@ -296,10 +296,30 @@ __device__ __forceinline__ void later_passes_dif(float (&vr)[E], float (&vi)[E],
     }
 }
 
+// Whether the exchange into pass P of a group of 2^M positions stays inside
+// one wave.  Between two full passes (RP = RB) position j moves from thread
+// (j mod 2^S') + ((j >> S) << S') to thread (j mod 2^S) + ((j >> (S + RB)) << S)
+// (S' = S - RB): both lie in the run of 2^S threads numbered from
+// (j >> (S + RB)) << S, so the exchange never leaves an aligned run of 2^S
+// consecutive threads.  When the group's threads are the consecutive lanes
+// 0 .. 2^(M-RB) - 1 of aligned runs (SYNC_T = 2^(M-RB)) and 2^S <= 64, each
+// run lies in one wave, and wave-level ordering suffices where SYNC_T alone
+// would ask for workgroup barriers.
+template <int M, int RB, int P, int SYNC_T>
+__host__ __device__ constexpr bool wave_local_exchange()
+{
+    return P >= 1 && P * RB < M && SYNC_T == (1 << (M - RB)) && SYNC_T > 64 && Pass<M, RB, P>::RP == RB &&
+           (1 << Pass<M, RB, P>::S) <= 64;
+}
+
 // Passes P, P+1, ... of a group of 2^M positions: exchange through LDS, then
 // the pass's stages (A, lo_g as for stages()).  SYNC_T is the thread count
 // whose exchange ordering is needed (the group's own T when its threads are
-// consecutive lanes; anything above 64 forces workgroup barriers).
+// consecutive lanes; anything above 64 forces workgroup barriers).  An
+// exchange that stays inside each wave (wave_local_exchange) orders only its
+// wave's accesses; the next exchange that does not then starts with a
+// workgroup barrier, so that no wave writes slots that another wave may still
+// be reading.
 template <int M, int RB, int P, bool SPLIT, int E, class TW, int A = 0, int SYNC_T = (1 << (M - RB))>
 __device__ __forceinline__ void later_passes(float (&vr)[E], float (&vi)[E], float* lr, float* li, int t,
                                              const float2* __restrict__ tw, int lo_g = 0)
@@ -308,22 +328,26 @@ __device__ __forceinline__ void later_passes(float (&vr)[E], float (&vi)[E], flo
         constexpr int LT = M - RB;
         using Prev = Pass<M, RB, P - 1>;
         using Cur = Pass<M, RB, P>;
+        constexpr bool LOCAL = wave_local_exchange<M, RB, P, SYNC_T>();
+        constexpr int XT = LOCAL ? 64 : SYNC_T;
+        if constexpr (!LOCAL && wave_local_exchange<M, RB, P - 1, SYNC_T>())
+            xsync<SYNC_T>();
         if constexpr (SPLIT) {  // one plane at a time through the same LDS
             lds_put<E, LT, Prev::S, Prev::RP, Cur::S, Cur::RP>(vr, lr, t);
-            xsync<SYNC_T>();
+            xsync<XT>();
             lds_get<E, LT, Cur::S, Cur::RP>(vr, lr, t);
-            xsync<SYNC_T>();
+            xsync<XT>();
             lds_put<E, LT, Prev::S, Prev::RP, Cur::S, Cur::RP>(vi, lr, t);
-            xsync<SYNC_T>();
+            xsync<XT>();
             lds_get<E, LT, Cur::S, Cur::RP>(vi, lr, t);
-            xsync<SYNC_T>();
+            xsync<XT>();
         } else {
             lds_put<E, LT, Prev::S, Prev::RP, Cur::S, Cur::RP>(vr, lr, t);
             lds_put<E, LT, Prev::S, Prev::RP, Cur::S, Cur::RP>(vi, li, t);
-            xsync<SYNC_T>();
+            xsync<XT>();
             lds_get<E, LT, Cur::S, Cur::RP>(vr, lr, t);
             lds_get<E, LT, Cur::S, Cur::RP>(vi, li, t);
-            xsync<SYNC_T>();
+            xsync<XT>();
         }
         stages<E, LT, Cur::S, Cur::RP, TW, A>(vr, vi, t, tw, lo_g);
         later_passes<M, RB, P + 1, SPLIT, E, TW, A, SYNC_T>(vr, vi, lr, li, t, tw, lo_g);
