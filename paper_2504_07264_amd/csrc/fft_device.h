@@ -263,15 +263,38 @@ struct PassD {
     static constexpr int S = M - RP0 - RB * P;
 };
 
+// Whether the DIF exchange into pass P stays inside one wave.  Pass P covers
+// bits S .. S+RB-1 of the position and the full pass P-1 the RB bits above;
+// position j moves from thread (j mod 2^(S+RB)) + ((j >> (S+2RB)) << (S+RB)) to
+// thread (j mod 2^S) + ((j >> (S+RB)) << S), both in the aligned run of
+// 2^(S+RB) consecutive threads numbered from (j >> (S+2RB)) << (S+RB).  With
+// 2^(S+RB) <= 64 that run lies in one wave.  S decreases from pass to pass,
+// so once an exchange is wave-local every later one is too.
+template <int M, int RB, int P>
+__host__ __device__ constexpr bool dif_wave_local_exchange()
+{
+    return P >= 1 && P < PassD<M, RB, 0>::NP && (1 << (M - RB)) > 64 && PassD<M, RB, P - 1>::RP == RB &&
+           (1 << (PassD<M, RB, P>::S + RB)) <= 64;
+}
+
+// Whether the last DIF exchange was ordered per wave only: the caller then
+// needs a workgroup barrier before its next LDS writes.
+template <int M, int RB>
+__host__ __device__ constexpr bool dif_last_exchange_local()
+{
+    return dif_wave_local_exchange<M, RB, PassD<M, RB, 0>::NP - 1>();
+}
+
 // DIF passes P, P+1, ...: exchange through LDS, then the pass's stages
-// (twiddle sources as in stages_dif).
+// (twiddle sources as in stages_dif).  Wave-local exchanges
+// (dif_wave_local_exchange) are ordered per wave.
 template <int M, int RB, int P, bool SPLIT, int E, class TW = TwTable<0>>
 __device__ __forceinline__ void later_passes_dif(float (&vr)[E], float (&vi)[E], float* lr, float* li, int t,
                                                  const float2* __restrict__ tw, const float2* __restrict__ tws)
 {
     if constexpr (P < PassD<M, RB, 0>::NP) {
         constexpr int LT = M - RB;
-        constexpr int T = 1 << LT;
+        constexpr int T = dif_wave_local_exchange<M, RB, P>() ? 64 : (1 << LT);
         using Prev = PassD<M, RB, P - 1>;
         using Cur = PassD<M, RB, P>;
         if constexpr (SPLIT) {

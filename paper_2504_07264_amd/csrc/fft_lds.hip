@@ -262,6 +262,10 @@ __device__ __forceinline__ void run_stages(float (&vr)[C::E], float (&vi)[C::E],
         stages_dif<E, LT, First::S, First::RP, TW>(vr, vi, t, tw, tws);
         if constexpr (C::NP > 1)
             later_passes_dif<M, RB, 1, C::SPLIT, E, TW>(vr, vi, lr, li, t, tw, tws);
+        // a last exchange ordered per wave: other waves may still be reading
+        // slots that the next LDS writes (output staging, next block) reuse
+        if constexpr (C::NP > 1 && dif_last_exchange_local<M, RB>())
+            __syncthreads();
     } else {
         stages<E, LT, 0, Pass<M, RB, 0>::RP>(vr, vi, t, tw);
         if constexpr (C::NP > 1)
