@@ -24,7 +24,11 @@
 //           no data moves between lanes.
 // The K order is the same slot (lane quarter q, register r) in both
 // operands of each product, so it only needs to be consistent, not equal to
-// any particular hardware order.
+// any particular hardware order.  Step 3's order is fixed by the accumulator
+// layout (slot (q, r) = plane r >= 4, index 4q + (r & 3)); step 1 reads its
+// data in the same order, and as C16 and S16 are symmetric, A3 is then, lane
+// by lane and register by register, the step-1 B operand: one set of
+// constant registers serves both steps.
 //
 // Split precision (FP32 accumulate): each operand v = hi + lo (+ lo2) in the
 // low-precision type; products are summed smallest first:
@@ -145,10 +149,12 @@ __device__ __forceinline__ void load_const(const float* tab, int mat, int lane,
 }
 
 constexpr int kWaves = 4;
-// LDS words of one staged plane: 256 floats with 16 pad words after each 128,
-// so the operand reads of lane quarters 0/1 (and 2/3) fall on different banks.
-constexpr int kPlaneWords = 256 + 32;
-__device__ __forceinline__ int pad256(int n) { return n + 16 * (n >> 7); }
+// LDS words of one staged plane: 256 floats with 16 pad words after each 64.
+// The operand reads and result writes touch n = 64q + 16r + c for lane
+// (q, c) and register r: lane quarter q then starts 80q words in, i.e. on
+// bank group 16q of 64 banks, and the 64 lanes hit 64 different banks.
+constexpr int kPlaneWords = 256 + 64;
+__device__ __forceinline__ int plane_word(int n) { return n + 16 * (n >> 6); }
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
@@ -243,7 +249,7 @@ __device__ __forceinline__ void load_rows_full(v4f (&in)[TPI][2], const float* x
 // TPI transforms per wave iteration; rows are staged through wave-private
 // LDS so that global loads and stores are 16-byte and fully coalesced.
 template <int MODE, int TPI>
-__global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(Prec<MODE>::PARTS == 2 ? 4 : 3)))
+__global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(4)))
 split_fft256_mfma_kernel(const float* xr, const float* xi, float* yr, float* yi, const float* __restrict__ consts,
                          const float2* __restrict__ tw256, int64_t batch)
 {
@@ -257,18 +263,18 @@ split_fft256_mfma_kernel(const float* xr, const float* xi, float* yr, float* yi,
     const int64_t nwaves = static_cast<int64_t>(gridDim.x) * kWaves;
     float* my = lds + (threadIdx.x >> 6) * (TPI * 2 * kPlaneWords);
 
-    V b1r[P::PARTS], b1i[P::PARTS], a3r[P::PARTS], a3i[P::PARTS];
-    load_const<MODE>(consts, 0, lane, b1r);
-    load_const<MODE>(consts, 1, lane, b1i);
-    load_const<MODE>(consts, 2, lane, a3r);
-    load_const<MODE>(consts, 3, lane, a3i);
+    // the constant operands of both contractions (real and imaginary rows)
+    V er[P::PARTS], ei[P::PARTS];
+    load_const<MODE>(consts, 0, lane, er);
+    load_const<MODE>(consts, 1, lane, ei);
     float2 w[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
         w[r] = tw256[((4 * q + r) * c) & 255];
 
-    // step-1 operand: lane (q, c) reads plane q >> 1 at n = 16 * (8 (q & 1) + r) + c
-    const int a_off = (q >> 1) * kPlaneWords + pad256(128 * (q & 1) + c);
+    // step-1 operand: lane (q, c), register r reads plane r >= 4 at
+    // n = 16 (4q + (r & 3)) + c (input index n1 = 4q + (r & 3), row n0 = c)
+    const int a_off = plane_word(64 * q + c);
     // the grid is resident: each wave loops with a stride and issues the
     // next rows' loads before the current rows' arithmetic
     const int64_t stride = nwaves * TPI;
@@ -285,7 +291,7 @@ split_fft256_mfma_kernel(const float* xr, const float* xi, float* yr, float* yi,
         for (int t = 0; t < TPI; ++t) {
 #pragma unroll
             for (int p = 0; p < 2; ++p)
-                *reinterpret_cast<v4f*>(my + (2 * t + p) * kPlaneWords + pad256(4 * lane)) = in[t][p];
+                *reinterpret_cast<v4f*>(my + (2 * t + p) * kPlaneWords + plane_word(4 * lane)) = in[t][p];
             shift[t] = MODE == kModeFP16X2 ? row_shift(in[t]) : 0;
         }
         wave_lds_sync();
@@ -306,15 +312,15 @@ split_fft256_mfma_kernel(const float* xr, const float* xi, float* yr, float* yi,
             float v[8];
 #pragma unroll
             for (int r = 0; r < 8; ++r)
-                v[r] = src[16 * r];
+                v[r] = src[(r >> 2) * kPlaneWords + 16 * (r & 3)];
             if (MODE == kModeFP16X2 && shift[t] != 0)  // wave-uniform
 #pragma unroll
                 for (int r = 0; r < 8; ++r)
                     v[r] = __builtin_ldexpf(v[r], -shift[t]);
             V a[P::PARTS];
             split8<MODE>(v, a);
-            const f32x4 xr4 = product<MODE>(a, b1r);
-            const f32x4 xi4 = product<MODE>(a, b1i);
+            const f32x4 xr4 = product<MODE>(a, er);
+            const f32x4 xi4 = product<MODE>(a, ei);
             // twiddle W256^(n0 k1), n0 = 4q + r, k1 = c; B3 slot r < 4 real, r >= 4 imaginary
             float z[8];
 #pragma unroll
@@ -324,8 +330,8 @@ split_fft256_mfma_kernel(const float* xr, const float* xi, float* yr, float* yi,
             }
             V b3[P::PARTS];
             split8<MODE>(z, b3);
-            const f32x4 yr4 = product<MODE>(a3r, b3);
-            const f32x4 yi4 = product<MODE>(a3i, b3);
+            const f32x4 yr4 = product<MODE>(er, b3);
+            const f32x4 yi4 = product<MODE>(ei, b3);
             // lane holds k2 = 4q + r, k1 = c: output index k1 + 16 k2 (the
             // transform's operand reads above are complete: the MFMAs used them)
             float* dr = my + 2 * t * kPlaneWords;
@@ -339,16 +345,16 @@ split_fft256_mfma_kernel(const float* xr, const float* xi, float* yr, float* yi,
                 }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                dr[pad256(c + 16 * (4 * q + r))] = outr[r];
-                di[pad256(c + 16 * (4 * q + r))] = outi[r];
+                dr[plane_word(c + 16 * (4 * q + r))] = outr[r];
+                di[plane_word(c + 16 * (4 * q + r))] = outi[r];
             }
         }
         wave_lds_sync();
 #pragma unroll
         for (int t = 0; t < TPI; ++t) {
             if (FULL || b0 + t < batch) {
-                const v4f o_r = *reinterpret_cast<const v4f*>(my + 2 * t * kPlaneWords + pad256(4 * lane));
-                const v4f o_i = *reinterpret_cast<const v4f*>(my + (2 * t + 1) * kPlaneWords + pad256(4 * lane));
+                const v4f o_r = *reinterpret_cast<const v4f*>(my + 2 * t * kPlaneWords + plane_word(4 * lane));
+                const v4f o_i = *reinterpret_cast<const v4f*>(my + (2 * t + 1) * kPlaneWords + plane_word(4 * lane));
                 __builtin_nontemporal_store(o_r, reinterpret_cast<v4f*>(yr + (b0 + t) * 256) + lane);
                 __builtin_nontemporal_store(o_i, reinterpret_cast<v4f*>(yi + (b0 + t) * 256) + lane);
             }

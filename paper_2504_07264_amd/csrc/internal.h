@@ -151,8 +151,8 @@ constexpr int kModeFP16X2 = 2;
 constexpr int kModeBF16X3 = 3;
 
 // 32-bit words of the per-mode constant table of the length-256 matrix-core
-// kernel: 4 operands x 3 parts x 64 lanes x 8 16-bit values.
-constexpr int kMfmaConstFloats = 4 * 3 * 64 * 8 / 2;
+// kernel: 2 operands x 3 parts x 64 lanes x 8 16-bit values.
+constexpr int kMfmaConstFloats = 2 * 3 * 64 * 8 / 2;
 
 // Host: constant operands of the length-256 matrix-core kernel for `mode`,
 // split from FP64 into parts exactly representable in the low-precision type

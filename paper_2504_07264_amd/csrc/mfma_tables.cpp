@@ -3,8 +3,12 @@
 // The kernel computes two 16-point DFTs per transform as real contractions
 // with the block matrix [[C16, S16], [-S16, C16]] of eq. (5) at N = 16
 // (c_kn = cos(2 pi k n / 16), s_kn = sin(2 pi k n / 16)).  Each lane of a
-// wave holds, for each of four constant operands, 8 entries (register r of
-// lane quarter q, column or row lane % 16).  The entries are formed in FP64
+// wave holds, for each of two constant operands (the real and the imaginary
+// output rows), 8 entries (register r of lane quarter q, index lane % 16).
+// C16 and S16 are symmetric, and both contractions order K alike (slot
+// (q, r) = plane r >= 4, n = 4q + (r & 3)), so the same registers are the B
+// operand of the first contraction (column k1 = lane % 16) and the A operand
+// of the second (row k2 = lane % 16).  The entries are formed in FP64
 // and split into hi (+ lo (+ lo2)) parts exactly representable in the
 // low-precision type; the FP16 lo part is scaled by 2^11.  The parts are
 // stored in the type's encoding, so that each lane loads one (operand, part)
@@ -73,19 +77,14 @@ void build_mfma256_constants(int mode, uint16_t* out)
     for (int lane = 0; lane < 64; ++lane) {
         const int q = lane >> 4, c = lane & 15;
         for (int r = 0; r < 8; ++r) {
-            // step 1, B operand: slot (q, r) = plane q >> 1, n1 = 8 (q & 1) + r; column k1 = c
-            const int n1 = 8 * (q & 1) + r;
-            const bool re = (q >> 1) == 0;
-            const double b1r = re ? cos16(n1 * c) : sin16(n1 * c);
-            const double b1i = re ? -sin16(n1 * c) : cos16(n1 * c);
-            // step 3, A operand: row k2 = c; slot (q, r) = real n0 = 4q + r for r < 4,
-            // imaginary n0 = 4q + r - 4 for r >= 4
-            const int n0 = 4 * q + (r & 3);
-            const bool re3 = r < 4;
-            const double a3r = re3 ? cos16(c * n0) : sin16(c * n0);
-            const double a3i = re3 ? -sin16(c * n0) : cos16(c * n0);
-            const double vals[4] = {b1r, b1i, a3r, a3i};
-            for (int mat = 0; mat < 4; ++mat) {
+            // slot (q, r): real part of input n = 4q + r for r < 4, imaginary
+            // part of n = 4q + r - 4 for r >= 4; output index c
+            const int n = 4 * q + (r & 3);
+            const bool re = r < 4;
+            const double er = re ? cos16(c * n) : sin16(c * n);
+            const double ei = re ? -sin16(c * n) : cos16(c * n);
+            const double vals[2] = {er, ei};
+            for (int mat = 0; mat < 2; ++mat) {
                 uint16_t parts[3];
                 split(vals[mat], mode, parts);
                 for (int k = 0; k < 3; ++k)
