@@ -86,11 +86,15 @@ template <int MODE>
 __device__ __forceinline__ void split8(const float (&v)[8], typename Prec<MODE>::V (&p)[Prec<MODE>::PARTS])
 {
     if constexpr (MODE == kModeFP16X2) {
+        // lo = (v - h) 2^11 rounded once to FP16: v - h and the scaling are
+        // exact, so the fused form below has the same value and lets the
+        // compiler read h as an FP16 operand (mixed-precision FMA) instead
+        // of converting it back first
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             const _Float16 h = static_cast<_Float16>(v[r]);
             p[0][r] = h;
-            p[1][r] = static_cast<_Float16>((v[r] - static_cast<float>(h)) * 2048.0f);
+            p[1][r] = static_cast<_Float16>(__builtin_fmaf(-static_cast<float>(h), 2048.0f, v[r] * 2048.0f));
         }
     } else {
 #pragma unroll
