@@ -477,9 +477,11 @@ def copy_ceiling(iters: int = MIN_ITERS, sets: int = 4):
     return out
 
 
-def dif_n1024(iters: int = MIN_ITERS, sets: int = 4):
+def dif_n1024(iters: int = MIN_ITERS, sets: int = 4, rounds: int = 5):
     """Forward N=1024 x 16384 through the decimation-in-frequency schedule
-    (eq. 9), same inputs as the headline: launch time statistics."""
+    (eq. 9), same inputs as the headline: launch time statistics, timed in
+    rounds interleaved with the default (DIT) schedule on the same buffers, so
+    that both see the same clocks."""
     import torch
 
     from paper_2504_07264_amd import Plan, binding, inputs
@@ -490,12 +492,20 @@ def dif_n1024(iters: int = MIN_ITERS, sets: int = 4):
     bufs = [(xr.to(dev), xi.to(dev), torch.empty_like(xr, device=dev), torch.empty_like(xi, device=dev))
             for _ in range(sets)]
     stream = torch.cuda.current_stream(dev)
-    with Plan(w.n, w.batch, binding.DIF) as plan:
+    with Plan(w.n, w.batch, binding.DIF) as plan, Plan(w.n, w.batch) as dit:
         for k in range(5):
             plan.exec(*bufs[k % sets])
-        us = stats_us(event_times(lambda k: plan.exec(*bufs[k % sets]), iters, stream))
+            dit.exec(*bufs[k % sets])
+        t_dif, t_dit = [], []
+        for _ in range(rounds):
+            t_dif += event_times(lambda k: plan.exec(*bufs[k % sets]), iters // rounds, stream)
+            t_dit += event_times(lambda k: dit.exec(*bufs[k % sets]), iters // rounds, stream)
+        us, us_dit = stats_us(t_dif), stats_us(t_dit)
         return {"workload": "split_fft_n1024_b16384 forward, decimation in frequency (eq. 9)", "us": us,
-                "GBps": round(16 * w.n * w.batch / us["median"] / 1e3, 1), "schedule": plan.describe()}
+                "GBps": round(16 * w.n * w.batch / us["median"] / 1e3, 1), "schedule": plan.describe(),
+                "dit_same_rounds_us": us_dit, "time_vs_dit": round(us["median"] / us_dit["median"], 3),
+                "from": "%d rounds, each %d groups of 4 launches of the DIF and then of the DIT schedule"
+                        % (rounds, iters // rounds)}
 
 
 def fused_schedule_flags(m: int):
