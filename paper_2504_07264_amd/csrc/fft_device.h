@@ -285,6 +285,11 @@ __host__ __device__ constexpr bool dif_last_exchange_local()
     return dif_wave_local_exchange<M, RB, PassD<M, RB, 0>::NP - 1>();
 }
 
+static_assert(dif_last_exchange_local<11, 4>() && dif_last_exchange_local<14, 4>() &&
+                  dif_last_exchange_local<13, 5>() && !dif_wave_local_exchange<14, 4, 2>() &&
+                  !dif_wave_local_exchange<14, 4, 1>() && !dif_last_exchange_local<10, 4>(),
+              "wave-local exchanges of the DIF passes");
+
 // DIF passes P, P+1, ...: exchange through LDS, then the pass's stages
 // (twiddle sources as in stages_dif).  Wave-local exchanges
 // (dif_wave_local_exchange) are ordered per wave.
@@ -334,6 +339,16 @@ __host__ __device__ constexpr bool wave_local_exchange()
     return P >= 1 && P * RB < M && SYNC_T == (1 << (M - RB)) && SYNC_T > 64 && Pass<M, RB, P>::RP == RB &&
            (1 << Pass<M, RB, P>::S) <= 64;
 }
+
+// The cases the position-map tests enumerate: with 16 elements per thread
+// the first exchange of 2^11 .. 2^14 stays in a wave and the second does not;
+// with 32, the first of 2^12 .. 2^15; a transform of one wave needs no rule,
+// and neither does a sync group other than the transform's own lanes.
+static_assert(wave_local_exchange<11, 4, 1, 128>() && wave_local_exchange<14, 4, 1, 1024>() &&
+                  !wave_local_exchange<14, 4, 2, 1024>() && !wave_local_exchange<14, 4, 3, 1024>() &&
+                  wave_local_exchange<15, 5, 1, 1024>() && !wave_local_exchange<10, 4, 1, 64>() &&
+                  !wave_local_exchange<14, 4, 1, 1025>(),
+              "wave-local exchanges of the DIT passes");
 
 // Passes P, P+1, ... of a group of 2^M positions: exchange through LDS, then
 // the pass's stages (A, lo_g as for stages()).  SYNC_T is the thread count
