@@ -761,7 +761,7 @@ const Variant kV12[] = {V<12, 4, 1, Y, Y, 2, 4, 2>(),    V<12, 5, 2, Y, Y, 2, 2>
                         V<12, 5, 2, Y, Y, Y, 2>(),       V<12, 5, 1, Y, Y, 2, 2, 2>(), V<12, 4, 2, Y, Y, 2, 4, 2>()};
 const Variant kV13[] = {V<13, 4, 1, Y, Y, 2, 4, 2>(),    V<13, 5, 1, Y, Y, 0, 2, 2>(), V<13, 5, 1, Y, Y, 2, 2, 2>(),
                         V<13, 4, 1, Y, Y, 2, 4, 2, Y>(), V<13, 5, 1, Y, Y, 2, 4, 2>(), V<13, 5, 1, _, Y, _, 1>()};
-const Variant kV14[] = {V<14, 4, 1, Y, Y, 2, 1, 2, Y>(), V<14, 4, 1, Y, Y, 2, 1, 1, Y>(), V<14, 4, 1, Y, Y, 3, 1, 2, Y>(),
+const Variant kV14[] = {V<14, 4, 1, Y, Y, 2, 1, 1, Y>(), V<14, 4, 1, Y, Y, 2, 1, 2, Y>(), V<14, 4, 1, Y, Y, 3, 1, 2, Y>(),
                         V<14, 5, 1, Y, Y, 2, 2, 2, Y>(), V<14, 4, 1, Y, Y, 2, 1, 2>(),    V<14, 5, 1, Y, Y, 3, 4, 2>(),
                         V<14, 5, 1, Y, Y, 3, 2, 2>(),    V<14, 5, 1, Y, Y, 2, 2, 2>()};
 const Variant kV15[] = {V<15, 5, 1, Y, Y, 3, 1, 2>(), V<15, 5, 1, Y, Y, _, 1>()};
