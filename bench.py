@@ -83,18 +83,26 @@ def event_times(fn, iters, stream, group: int = 4):
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "split_fft_n1024_b16384_hbm_traffic.md")
 
 
-def kernel_source_hash() -> str:
-    """sha256 of the forward kernel's device source (fft_lds.hip, then the
-    stage code it includes, fft_device.h) with comments and blank lines
-    removed (a comment edit does not invalidate a measurement)."""
+def code_hash(texts) -> str:
+    """sha256 of source texts with line comments, trailing blanks and blank
+    lines removed (a comment edit does not change it)."""
     import re
 
     code = []
-    for name in ("fft_lds.hip", "fft_device.h"):
-        with open(os.path.join(ROOT, "paper_2504_07264_amd", "csrc", name)) as f:
-            lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in f.read().splitlines()]
+    for text in texts:
+        lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines()]
         code.append("\n".join(ln for ln in lines if ln.strip()))
     return hashlib.sha256("\n".join(code).encode()).hexdigest()
+
+
+def kernel_source_hash() -> str:
+    """code_hash of the forward kernel's device source (fft_lds.hip, then the
+    stage code it includes, fft_device.h)."""
+    texts = []
+    for name in ("fft_lds.hip", "fft_device.h"):
+        with open(os.path.join(ROOT, "paper_2504_07264_amd", "csrc", name)) as f:
+            texts.append(f.read())
+    return code_hash(texts)
 
 
 def measured_traffic():
