@@ -98,8 +98,9 @@ typedef enum {
                                range (any finite input)                         */
 #define SPLIT_DFT_BF16X3 3u /* bf16 hi+mid+lo, 6 products                       */
 /* Bits 8-15: 0 = default kernel schedule, k = compiled FP32 schedule k-1
- * (used by tuning).  At n = 2^15 and 2^16 the last compiled schedule runs both
- * passes of eq. (6) in one persistent launch, handing each transform's
+ * (used by tuning; split_dft_plan_describe names each).  At n = 2^15 and 2^16 one
+ * compiled schedule, described as "fused", runs both passes of eq. (6) in one
+ * persistent launch, handing each transform's
  * intermediate between the workgroups of one XCD through a ring in the
  * workspace that the XCD's L2 caches (Section III's regrouped factors); its
  * workspace is the ring (24 / 32 MiB) whatever the batch.  Its workgroups wait
