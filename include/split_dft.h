@@ -98,15 +98,15 @@ typedef enum {
                                range (any finite input)                         */
 #define SPLIT_DFT_BF16X3 3u /* bf16 hi+mid+lo, 6 products                       */
 /* Bits 8-15: 0 = default kernel schedule, k = compiled FP32 schedule k-1
- * (used by tuning; split_dft_plan_describe names each).  At n = 2^15 and 2^16 one
- * compiled schedule, described as "fused", runs both passes of eq. (6) in one
- * persistent launch, handing each transform's
- * intermediate between the workgroups of one XCD through a ring in the
- * workspace that the XCD's L2 caches (Section III's regrouped factors); its
- * workspace is the ring (24 / 32 MiB) whatever the batch.  Its workgroups wait
- * for each other: at least 4 (2^15) or 8 (2^16) of them must be able to run at
- * once on each XCD, which holds unless other work fills the device for seconds
- * (a wait that times out ends the launch with undefined results). */
+ * (used by tuning; split_dft_plan_describe names each).  At n = 2^15 and
+ * 2^16 one compiled schedule, described as "fused", runs both passes of eq.
+ * (6) in one persistent launch, handing each transform's intermediate
+ * between the workgroups of one XCD through a ring in the workspace that the
+ * XCD's L2 caches (Section III's regrouped factors); its workspace is the
+ * ring (24 / 32 MiB) whatever the batch.  Its workgroups wait for each
+ * other: at least 4 (2^15) or 8 (2^16) of them must be able to run at once
+ * on each XCD, which holds unless other work fills the device for seconds (a
+ * wait that times out ends the launch with undefined results). */
 /* Bit 24: evaluate through the decimation-in-frequency factorisation of
  * eq. (9), y_2N = S D^(1) W^(1) ... D^(m) W^(m) x_2N (stages m down to 1,
  * butterfly before rotation, the bit reversal last), FP32, every n (two
