@@ -746,7 +746,7 @@ const Variant kV7[] = {V<7, 4, 32, Y, Y, 2, 4, 1, Y>(), V<7, 4, 16, _, Y, 2, 4, 
                        V<7, 4, 32, _, _, _, 1>()};
 const Variant kV8[] = {V<8, 4, 16, Y, Y, Y, 4, Y>(), V<8, 4, 16, Y, Y, 2, 4, 1, Y>(), V<8, 4, 32, Y, Y, 2, 4, 1, Y>(),
                        V<8, 4, 16, _, _, _, 1>()};
-const Variant kV9[] = {V<9, 4, 8, Y, Y, 2, 4, 2, Y>(), V<9, 4, 8, Y, Y, 2, 4, 1, Y>(), V<9, 4, 4, Y, Y, 2, 4, 2, Y>(),
+const Variant kV9[] = {V<9, 4, 8, Y, Y, 2, 4, 1, Y>(), V<9, 4, 8, Y, Y, 2, 4, 2, Y>(), V<9, 4, 4, Y, Y, 2, 4, 2, Y>(),
                        V<9, 4, 8, Y, Y, Y, 4, Y>(),    V<9, 4, 8, _, Y, Y, 1>(),       V<9, 4, 8, Y, Y, 2, 4, 2>()};
 const Variant kV10[] = {V<10, 4, 4, _, Y, 2, 4, 2, Y>(), V<10, 4, 4, Y, Y, 2, 4, 2, Y>(), V<10, 4, 4, Y, Y, 1, 4, 2, Y>(),
                         V<10, 4, 4, Y, Y, 2, 3, 2, Y>(), V<10, 4, 8, Y, Y, 2, 3, 2, Y>(), V<10, 4, 2, Y, Y, 2, 4, 2, Y>(),
@@ -786,7 +786,7 @@ const Variant kD5[] = {DV<5, 4, 64, _, Y, 2, 4, 1, Y>(), DV<5, 4, 64, _, _, _, 1
 const Variant kD6[] = {DV<6, 4, 64, _, Y, 2, 4, 1, Y>(), DV<6, 4, 32, _, _, _, 1>()};
 const Variant kD7[] = {DV<7, 4, 32, Y, Y, 2, 4, 1, Y>(), DV<7, 4, 16, _, _, _, 1>()};
 const Variant kD8[] = {DV<8, 4, 16, Y, Y, 2, 4, 1, Y>(), DV<8, 4, 16, Y, _, _, 4>()};
-const Variant kD9[] = {DV<9, 4, 8, Y, Y, 2, 4, 2, Y>(), DV<9, 4, 8, Y, Y, 2, 4, 1, Y>(), DV<9, 4, 8, Y, Y, _, 4>()};
+const Variant kD9[] = {DV<9, 4, 8, Y, Y, 2, 4, 1, Y>(), DV<9, 4, 8, Y, Y, 2, 4, 2, Y>(), DV<9, 4, 8, Y, Y, _, 4>()};
 const Variant kD10[] = {DV<10, 4, 4, _, Y, 2, 4, 2, Y>(), DV<10, 4, 4, _, Y, 2, 4, 1, Y>(), DV<10, 4, 4, Y, Y, _, 4>()};
 // (the last DIF pass scatters its direct stores once T > 64: stage them)
 const Variant kD11[] = {DV<11, 4, 2, Y, Y, 2, 4, 1>(), DV<11, 4, 2, Y, Y, 2, 4, 2>(), DV<11, 4, 2, Y, Y, _, 4>()};

@@ -203,6 +203,8 @@ def main(argv=None):
     ap.add_argument("--cache", default=None)
     ap.add_argument("--iters", type=int, default=20)
     ap.add_argument("--dif", action="store_true", help="tune the decimation-in-frequency schedules")
+    ap.add_argument("--all", action="store_true",
+                    help="print every schedule's time (first pass and, for the finalists, the rounds' median)")
     args = ap.parse_args(argv)
     for n in [int(x) for x in args.lengths.split(",") if x]:
         batch = max(1, args.points // n)
@@ -210,8 +212,10 @@ def main(argv=None):
             continue
         best, t = tune_length(n, batch, args.iters, dif=args.dif)
         record(length_key(n, batch, args.dif), best, t, args.cache)
-        print(json.dumps({"n": n, "batch": batch, "dif": args.dif, "best_flags": best, "best": t[best],
-                          "candidates": len(t)}), flush=True)
+        line = {"n": n, "batch": batch, "dif": args.dif, "best_flags": best, "best": t[best], "candidates": len(t)}
+        if args.all:
+            line["schedules"] = [dict(t[f], flags=f) for f in sorted(t)]
+        print(json.dumps(line), flush=True)
     if args.ragged:
         from . import inputs
 
