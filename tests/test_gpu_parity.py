@@ -216,7 +216,8 @@ def test_adjoint_full_size_n4096():
 # resident workgroup of a persistent schedule several blocks
 @pytest.mark.parametrize("n,batch,dif", [(1024, 37, False), (1024, 16387, False), (64, 262147, False),
                                          (8192, 2051, False), (1024, 16387, True), (16384, 1027, True),
-                                         (32768, 41, True), (65536, 300, True)])
+                                         (32768, 41, True), (65536, 300, True), (512, 32771, False),
+                                         (512, 32771, True), (16384, 1027, False), (16384, 3, False)])
 def test_in_place_and_swapped_planes(n, batch, dif):
     xr, xi = inputs.draw_planes(n, batch, "normal", 7)
     mirror = oracle.split_fft_dif_f32 if dif else oracle.split_fft_f32
